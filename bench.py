@@ -1,0 +1,203 @@
+"""Benchmark: GDOF/s per SSP-RK3 stage of the P3 Euler DG hot path on one MI355X.
+
+Workload (the precision-form configuration): isentropic vortex (strength 5, Mach 0.5) on
+the periodic [0,10]^3 cube split into 64^3 hexahedra x 6 = 1,572,864 tets, P3 (20 modes,
+5 variables: 157,286,400 DOF), element order shuffled from a seed and renumbered along a
+Hilbert curve.  One step = one SSP-RK3 step = three fused residual+update launches.
+
+The headline value is the mixed bf16 path (bf16 MFMA contractions with fp32 accumulation,
+fp32 fluxes, fp64 state); the same workload is also timed in fp32, fp16-mixed and fp64, the
+residual-only kernel is timed, and the mixed result after the timed steps is compared with
+the fp64 GPU result (relative L2 per variable).  cpu_baseline is the FP64 CPU oracle on a
+16^3 x 6 sample of the same problem.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from synthetic import fields, kuhn_cube  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+
+
+def stage_bytes(n_elem: int, n_modes: int, state_bytes: int) -> float:
+    """Algorithmic HBM bytes of one SSP-RK3 step (three stages): per element the state read
+    (U_in), the stage base U0 (stages 2 and 3), the result write, the geometry (9 + 1 fp64)
+    and the topology (4 neighbour ids + packed face codes, int32)."""
+    st = 5 * n_modes * state_bytes
+    per_elem = (2 * st) + 2 * (3 * st) + 3 * (80 + 20)
+    return float(n_elem) * per_elem
+
+
+def timed(fn, steps: int, warmup: int) -> float:
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        fn()
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / 1000.0
+
+
+def run_gpu(args):
+    from paper_2209_01877_amd import Solver
+
+    n = args.n
+    p = args.p
+    mesh = kuhn_cube(n, length=10.0, shuffle_seed=2209, vid_seed=2210)
+    vortex = lambda x: fields.isentropic_vortex(x, length=10.0, beta=5.0, mach=0.5)  # noqa: E731
+    results = {}
+    states = {}
+    dt = None
+    for prec in args.precisions:
+        s = Solver(p, prec)
+        t0 = time.time()
+        s.upload(mesh, renumber=args.renumber)
+        upload_s = time.time() - t0
+        U = s.project_fn(vortex)
+        if dt is None:
+            # CFL 0.2 rule on the undisturbed spacing: d_K >= 0.41 h for the Kuhn split,
+            # max |u| + c <= 3.1 for this vortex
+            h = 10.0 / n
+            dt = 0.2 * 0.41 * h / ((2 * p + 1) * 3.1)
+        work = s.new_work()
+        U0 = U.clone()
+        step = lambda: s.rk_step(U, dt, 1, work)  # noqa: E731
+        t = timed(step, args.steps, args.warmup)
+        s.sync()
+        dof = mesh.n_elem * s.n_modes * 5
+        stages = 3 * args.steps
+        gdofs = dof * stages / t / 1e9
+        R = s.new_state()
+        tr = timed(lambda: s.residual(U, R), args.steps, args.warmup)
+        # reproducible end state: restart from U0 for exactly `steps` steps
+        U.copy_(U0)
+        s.rk_step(U, dt, args.steps, work)
+        states[prec] = s.get_state(U)
+        s.sync()
+        sb = 4 if prec == "fp32" else 8
+        results[prec] = {
+            "gdof_per_s_per_stage": gdofs,
+            "ms_per_step": 1e3 * t / args.steps,
+            "residual_gdof_per_s": dof * args.steps / tr / 1e9,
+            "residual_ms": 1e3 * tr / args.steps,
+            "stage_hbm_gb_per_s": stage_bytes(mesh.n_elem, s.n_modes, sb) * args.steps / t / 1e9,
+            "upload_s": upload_s,
+        }
+        del s, U, U0, work, R
+        torch.cuda.empty_cache()
+    if "fp64" in states:
+        ref = states["fp64"]
+        for prec, U in states.items():
+            diff = (U - ref).pow(2).sum(dim=(0, 2)).sqrt()
+            norm = ref.pow(2).sum(dim=(0, 2)).sqrt()
+            results[prec]["rel_l2_vs_fp64"] = (diff / torch.where(norm > 0, norm, torch.ones_like(norm))).tolist()
+    return mesh, dt, results
+
+
+def cpu_baseline(p: int, n_cpu: int, steps: int):
+    from oracle.dg import DG
+
+    torch.set_num_threads(max(1, len(os.sched_getaffinity(0))))
+    mesh = kuhn_cube(n_cpu, length=10.0, shuffle_seed=2209, vid_seed=2210)
+    dg = DG(p, mesh.elem_vid, mesh.elem_xyz)
+    U = dg.project(lambda x: fields.isentropic_vortex(x, length=10.0))
+    dt = 0.2 * 0.41 * (10.0 / n_cpu) / ((2 * p + 1) * 3.1)
+    U = dg.rk3_step(U, dt)  # warm-up
+    t0 = time.time()
+    for _ in range(steps):
+        U = dg.rk3_step(U, dt)
+    t = time.time() - t0
+    dof = mesh.n_elem * dg.Np * 5
+    return {
+        "value": dof * 3 * steps / t / 1e9,
+        "unit": "GDOF/s per RK stage",
+        "cores": torch.get_num_threads(),
+        "kind": "oracle",
+        "sample": f"P3 vortex on {n_cpu}^3 x 6 = {mesh.n_elem} tets, {steps} SSP-RK3 steps, fp64 torch-CPU, "
+                  f"face-centric, untuned ({t:.1f} s)",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=64, help="hexahedra per cube edge")
+    ap.add_argument("--p", type=int, default=3)
+    ap.add_argument("--renumber", default="hilbert")
+    ap.add_argument("--precisions", default="bf16,fp32,fp16,fp64")
+    ap.add_argument("--cpu-n", type=int, default=16)
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    args.precisions = args.precisions.split(",")
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is "
+              "documented but not built", file=sys.stderr)
+        sys.exit(2)
+    if "RANK" in os.environ and int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py is single-GPU; launch it without torch.distributed", file=sys.stderr)
+        sys.exit(2)
+    mesh, dt, res = run_gpu(args)
+    head = args.precisions[0]
+    r = res[head]
+    st_bytes = 4 if head == "fp32" else 8
+    n_modes = (args.p + 1) * (args.p + 2) * (args.p + 3) // 6
+    achieved = stage_bytes(mesh.n_elem, n_modes, st_bytes) / 3.0 / (r["ms_per_step"] / 3.0 / 1e3) / 1e9
+    line = {
+        "metric": "GDOF/s per RK stage (P3 Euler), mixed vs FP32 at stated err; adjoint/fwd time",
+        "value": r["gdof_per_s_per_stage"],
+        "unit": "GDOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": head,
+        "data": "synthetic",
+        "config": {
+            "workload": f"isentropic vortex, P{args.p}, periodic {args.n}^3 x 6 Kuhn tets "
+                        f"({mesh.n_elem} elements), shuffled + {args.renumber} renumbering, SSP-RK3, dt {dt:.3e}",
+            "n_elem": mesh.n_elem,
+            "order": args.p,
+            "dof": mesh.n_elem * n_modes * 5,
+            "precision": head,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+        },
+        "per_precision": res,
+    }
+    if "fp32" in res and head != "fp32":
+        line["speedup_vs_fp32"] = r["gdof_per_s_per_stage"] / res["fp32"]["gdof_per_s_per_stage"]
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(args.p, args.cpu_n, args.cpu_steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,187 @@
+/*
+ * tetdg — explicit modal DG residual and SSP-RK3 stage update for the 3-D
+ * compressible Euler equations on affine tetrahedra, on one MI355X (gfx950).
+ *
+ * The method is the one of arXiv 2209.01877, Sec. II: conserved variables
+ * U = (rho, rho u, rho v, rho w, E) (Sec. II.A, eqs. 1-4, inviscid), a modal
+ * expansion U_h = sum_j c_j(t) phi_j(x) per element (Sec. II.B, eq. 10) and the
+ * weak form of eq. 11 with element and face Gaussian integrals, advanced by an
+ * explicit Runge-Kutta scheme (Sec. III).  The choices the paper leaves open are
+ * fixed as follows and are part of this interface:
+ *
+ *   basis       orthonormal PKD polynomials of total degree <= p on the unit tet
+ *               (0,0,0),(1,0,0),(0,1,0),(0,0,1), scaled so 6*int phi_m phi_n = delta_mn
+ *               (phi_0 = 1, so c_0 is the cell mean); ordering by total degree d,
+ *               then k = 0..d, j = 0..d-k, i = d-j-k of the collapsed-coordinate form.
+ *   element map each tet's vertices taken in ascending global vertex id,
+ *               x = X0 + [X1-X0 | X2-X0 | X3-X0] xi.  Coefficients refer to this map.
+ *   quadrature  collapsed Gauss-Jacobi, n = p+1 points per direction (tet n^3,
+ *               triangle n^2), exact to degree 2p+1.
+ *   face flux   Rusanov (local Lax-Friedrichs), lambda = max(|u.n|+c) over both
+ *               sides per quadrature point.  The paper uses Roe.
+ *   boundaries  ghost states: farfield = free stream, slip wall = mirrored normal
+ *               momentum (eq. 11 boundary-face term).
+ *   time        SSP-RK3 in Shu-Osher form (the paper uses explicit 2nd-order RK).
+ *
+ * Conventions for every call:
+ *   - The return value is a tdg_status; nothing throws across this interface.
+ *     On failure tdg_last_error(ctx) describes it (valid until the next call on ctx).
+ *   - "device" pointers are HIP device memory owned by the caller (e.g. torch
+ *     tensors); "host" pointers are ordinary host memory, read during the call.
+ *   - Compute calls are asynchronous on the given hipStream_t (passed as void*,
+ *     NULL = the null stream).  Kernel-side faults surface on the next
+ *     synchronisation; tdg_sync_check() synchronises and reports them.
+ *   - The library allocates no device memory after tdg_mesh_bind().
+ *   - A context is not thread-safe; distinct contexts are independent.
+ *   - U, R, W and Ubar must not alias, except U in tdg_rk_step (updated in place).
+ */
+#ifndef TETDG_H
+#define TETDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tdg_ctx tdg_ctx;
+
+typedef enum {
+  TDG_OK = 0,
+  TDG_ERR_INVALID_ARG = -1, /* bad argument: null pointer, size, enum, order */
+  TDG_ERR_MESH = -2,        /* degenerate element, unmatched or over-shared face */
+  TDG_ERR_STATE = -3,       /* call out of order (no mesh, not bound) */
+  TDG_ERR_HIP = -4,         /* HIP runtime error (launch, copy, async fault) */
+  TDG_ERR_UNSUPPORTED = -5, /* valid request this build does not implement */
+  TDG_ERR_NOMEM = -6        /* host allocation failed or device buffer too small */
+} tdg_status;
+
+typedef enum {
+  TDG_FP64 = 0,       /* state, contractions and fluxes in double */
+  TDG_FP32 = 1,       /* state, contractions and fluxes in float */
+  TDG_MIXED_BF16 = 2, /* FP64 state; contractions bf16 x bf16 -> fp32 on MFMA; fluxes fp32 */
+  TDG_MIXED_FP16 = 3  /* as above with fp16 operands */
+} tdg_precision;
+
+typedef enum {
+  TDG_RENUM_NONE = 0,   /* keep the caller's element order */
+  TDG_RENUM_RCM = 1,    /* reverse Cuthill-McKee on the face-adjacency graph (Sec. III.B) */
+  TDG_RENUM_MORTON = 2, /* Morton (Z-order) curve of element centroids */
+  TDG_RENUM_HILBERT = 3 /* Hilbert curve of element centroids */
+} tdg_renumber;
+
+typedef enum { TDG_BC_FARFIELD = 1, TDG_BC_SLIPWALL = 2 } tdg_bc;
+
+/* ------------------------------------------------------------------ context */
+
+/* Create a context for polynomial order p (1..4) and a precision mode.  gamma is the
+ * ratio of specific heats (Sec. II.A, eq. 4).  *out receives the new context.
+ * Errors: TDG_ERR_INVALID_ARG (p, precision, gamma <= 1, out NULL), TDG_ERR_NOMEM. */
+int tdg_create(int order_p, int precision, double gamma, tdg_ctx** out);
+
+/* Release a context and its host memory; device memory stays with the caller. NULL is a no-op. */
+void tdg_destroy(tdg_ctx* ctx);
+
+/* Text of the last error on ctx ("" if none).  ctx may be NULL (then a static message). */
+const char* tdg_last_error(const tdg_ctx* ctx);
+
+/* Problem sizes: modes N_p, volume points N_q, points per face N_f. */
+int tdg_sizes(const tdg_ctx* ctx, int* n_modes, int* n_vol_points, int* n_face_points);
+
+/* ------------------------------------------------------------------ mesh */
+
+/* Upload a tetrahedral mesh (host arrays, copied).  Builds the face adjacency by
+ * matching sorted vertex-id triples, tags boundary faces, computes FP64 geometry and
+ * renumbers the elements (the grid renumbering of Sec. III.B: RCM, or a space-filling
+ * curve).  The renumbering runs once, before time stepping.
+ *   elem_vid   host int64 [n_elem][4]   global vertex ids (on a torus: periodic ids)
+ *   elem_xyz   host double [n_elem][4][3] vertex coordinates, per element, unwrapped
+ *   bface_vid  host int64 [n_bface][3]  boundary faces (any vertex order), may be NULL if 0
+ *   bface_tag  host int32 [n_bface]     TDG_BC_FARFIELD or TDG_BC_SLIPWALL
+ *   renumber   a tdg_renumber value
+ *   perm_new_to_old  host int64 [n_elem] out (may be NULL): internal index -> caller index
+ * Errors: TDG_ERR_INVALID_ARG; TDG_ERR_MESH for a zero-volume element, a face shared by
+ * more than two elements, or an unmatched face that is not a listed boundary face. */
+int tdg_mesh_upload(tdg_ctx* ctx, int64_t n_elem, const int64_t* elem_vid, const double* elem_xyz,
+                    int64_t n_bface, const int64_t* bface_vid, const int32_t* bface_tag, int renumber,
+                    int64_t* perm_new_to_old);
+
+/* Bytes of device memory the uploaded mesh and reference tables need (caller allocates). */
+int tdg_mesh_device_bytes(const tdg_ctx* ctx, size_t* bytes);
+
+/* Copy mesh arrays and reference tables into dev_buf (device, >= the size above, 256-byte
+ * aligned) on the stream and wait for the copy.  dev_buf must stay allocated while the
+ * context computes.  Errors: TDG_ERR_STATE (no mesh), TDG_ERR_INVALID_ARG, TDG_ERR_HIP. */
+int tdg_mesh_bind(tdg_ctx* ctx, void* dev_buf, size_t bytes, void* hip_stream);
+
+/* Free-stream primitive state (rho, u, v, w, p) used as the farfield ghost (host array). */
+int tdg_set_farfield(tdg_ctx* ctx, const double prim[5]);
+
+/* Mesh statistics after renumbering (host int64 out[6]): n_elem, n_elem_pad,
+ * interior faces, boundary faces, max |i - j| over face neighbours (bandwidth),
+ * and the number of neighbour pairs with |i - j| < 64. */
+int tdg_mesh_stats(const tdg_ctx* ctx, int64_t out[6]);
+
+/* ------------------------------------------------------------------ state */
+
+/* Internal state: [5][N_p][n_elem_pad] in renumbered element order (element index
+ * fastest), double for TDG_FP64 and the mixed modes, float for TDG_FP32.
+ * User state:     [n_elem][5][N_p] double, caller's element order. */
+int tdg_state_elems(const tdg_ctx* ctx, int64_t* n_elem_pad);
+int tdg_state_bytes(const tdg_ctx* ctx, size_t* bytes);
+
+/* User (device, double) -> internal (device).  Padding elements are set to a copy of element 0. */
+int tdg_set_state(tdg_ctx* ctx, const double* U_user, void* U_int, void* hip_stream);
+/* Internal (device) -> user (device, double). */
+int tdg_get_state(tdg_ctx* ctx, const void* U_int, double* U_user, void* hip_stream);
+
+/* Physical coordinates of the volume quadrature points, device double [n_elem][N_q][3],
+ * caller's element order (for evaluating initial fields). */
+int tdg_volume_points(tdg_ctx* ctx, double* xyz_user, void* hip_stream);
+
+/* L2 projection of a primitive field sampled at the volume points (device double
+ * [n_elem][N_q][5], caller's order) onto the basis: c_i = 6 sum_q w_q U(prim_q) phi_i(xi_q),
+ * written as an internal state. */
+int tdg_project(tdg_ctx* ctx, const double* prim_user, void* U_int, void* hip_stream);
+
+/* ------------------------------------------------------------------ hot path */
+
+/* R = M^-1 (V - S) for internal state U (Sec. II.B, eq. 11, inviscid):
+ *   V_i = int_K F(U_h) . grad phi_i,  S_i = sum_f int_f Fhat(U-, U+, n) phi_i,  M = |K| I.
+ * Each element evaluates its own four faces, reading its neighbours' coefficients, so
+ * the face integral reaches both neighbours without atomics.  R has U's layout. */
+int tdg_residual(tdg_ctx* ctx, const void* U, void* R, void* hip_stream);
+
+/* n_steps SSP-RK3 steps of size dt on U (internal, in place):
+ *   U1 = U + dt R(U);  U2 = 3/4 U + 1/4 (U1 + dt R(U1));  U <- 1/3 U + 2/3 (U2 + dt R(U2)).
+ * work: device, two internal states.  One fused residual+update launch per stage. */
+int tdg_rk_step(tdg_ctx* ctx, void* U, void* work, double dt, int n_steps, void* hip_stream);
+
+/* Vector-Jacobian product Ubar = (dR/dU)^T W at U (all internal layout; Ubar overwritten).
+ * Element-centric: each element gathers U and W of its neighbours and applies the
+ * transposed interpolation, flux Jacobians and transposed lift of its own and its
+ * neighbours' shared faces; no atomics.  FP64 and FP32 modes; the mixed modes compute
+ * the adjoint in FP64.  At exact ties of max(lambda-, lambda+) the derivative is split
+ * evenly, and d|x|/dx = 0 at x = 0. */
+int tdg_residual_vjp(tdg_ctx* ctx, const void* U, const void* W, void* Ubar, void* hip_stream);
+
+/* Synchronise the stream; map a pending asynchronous HIP error to TDG_ERR_HIP. */
+int tdg_sync_check(tdg_ctx* ctx, void* hip_stream);
+
+/* ------------------------------------------------------------------ host-only checks */
+
+/* Reference tables computed by this library, no GPU needed.  which:
+ *   0 volume points [N_q][3]      1 volume weights [N_q]
+ *   2 face points (s,t) [N_f][2]  3 face weights [N_f]
+ *   4 basis at volume points [N_q][N_p]
+ *   5 reference gradients [3][N_q][N_p]
+ *   6 basis at face points [4][N_f][N_p]
+ * out may be NULL to query *need (element count).  Errors: TDG_ERR_INVALID_ARG,
+ * TDG_ERR_NOMEM when cap < need. */
+int tdg_debug_tables(int order_p, int which, double* out, size_t cap, size_t* need);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TETDG_H */

@@ -1,0 +1,141 @@
+// Device-side building blocks of the DG kernels: MFMA precision traits, the
+// Euler flux at a point, the Rusanov face flux with an area-weighted normal,
+// and boundary ghost states.  Header-only, included by the .hip files.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "dg_common.hpp"
+
+namespace tetdg {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
+
+// ---------------------------------------------------------------- precision traits
+// S  : storage type of the state (global memory)
+// T  : arithmetic type of the pointwise fluxes
+// Op : MFMA operand type per lane, KW values per lane per slot
+struct PrecF64 {
+  using S = double;
+  using T = double;
+  using Op = double;
+  using Acc = d4_t;
+  static constexpr int KW = 1;
+  static constexpr bool f64 = true;
+  static constexpr bool mixed = false;
+  __device__ static Acc mfma(Op a, Op b, Acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static Op op1(T x) { return x; }
+};
+struct PrecF32 {
+  using S = float;
+  using T = float;
+  using Op = float;
+  using Acc = f4_t;
+  static constexpr int KW = 1;
+  static constexpr bool f64 = false;
+  static constexpr bool mixed = false;
+  __device__ static Acc mfma(Op a, Op b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static Op op1(T x) { return x; }
+};
+struct PrecBF16 {
+  using S = double;
+  using T = float;
+  using Op = bf8_t;
+  using E1 = __bf16;
+  using Acc = f4_t;
+  static constexpr int KW = 8;
+  static constexpr bool f64 = false;
+  static constexpr bool mixed = true;
+  __device__ static Acc mfma(Op a, Op b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+};
+struct PrecF16 {
+  using S = double;
+  using T = float;
+  using Op = h8_t;
+  using E1 = _Float16;
+  using Acc = f4_t;
+  static constexpr int KW = 8;
+  static constexpr bool f64 = false;
+  static constexpr bool mixed = true;
+  __device__ static Acc mfma(Op a, Op b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
+};
+
+template <class Pr>
+__device__ __forceinline__ int drow_of(int g, int j) {
+  return drow(Pr::f64, g, j);
+}
+
+// ---------------------------------------------------------------- Euler physics
+// Contravariant flux rows y_d = sum_e M[d][e] F_e(U) for d = 0..2, where F_e is the
+// Euler flux in direction e (eq. 2, 3-D) and M = |det J| J^-1.
+template <class T>
+__device__ __forceinline__ void contra_flux(const T u[5], const T M[9], T gm1, T y[3][5]) {
+  const T rho = u[0];
+  const T ir = T(1) / rho;
+  const T vx = u[1] * ir, vy = u[2] * ir, vz = u[3] * ir;
+  const T p = gm1 * (u[4] - T(0.5) * (u[1] * vx + u[2] * vy + u[3] * vz));
+  const T ep = u[4] + p;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const T th = M[3 * d + 0] * vx + M[3 * d + 1] * vy + M[3 * d + 2] * vz;
+    y[d][0] = rho * th;
+    y[d][1] = u[1] * th + p * M[3 * d + 0];
+    y[d][2] = u[2] * th + p * M[3 * d + 1];
+    y[d][3] = u[3] * th + p * M[3 * d + 2];
+    y[d][4] = ep * th;
+  }
+}
+
+// Rusanov flux through an area-weighted normal N (|N| = nn):
+//   Fhat = (F(um).N + F(up).N)/2 - max(|um.N| + c- nn, |up.N| + c+ nn)/2 (up - um)
+template <class T>
+__device__ __forceinline__ void rusanov_n(const T um[5], const T up[5], const T N[3], T nn, T gamma, T out[5]) {
+  const T gm1 = gamma - T(1);
+  const T irm = T(1) / um[0], irp = T(1) / up[0];
+  const T unm = (um[1] * N[0] + um[2] * N[1] + um[3] * N[2]) * irm;
+  const T unp = (up[1] * N[0] + up[2] * N[1] + up[3] * N[2]) * irp;
+  const T pm = gm1 * (um[4] - T(0.5) * (um[1] * um[1] + um[2] * um[2] + um[3] * um[3]) * irm);
+  const T pp = gm1 * (up[4] - T(0.5) * (up[1] * up[1] + up[2] * up[2] + up[3] * up[3]) * irp);
+  const T cm = sqrt(gamma * pm * irm), cp = sqrt(gamma * pp * irp);
+  const T lm = fabs(unm) + cm * nn, lp = fabs(unp) + cp * nn;
+  const T lam = lm > lp ? lm : lp;
+  const T h = T(0.5);
+  out[0] = h * (um[0] * unm + up[0] * unp) - h * lam * (up[0] - um[0]);
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    out[1 + d] = h * (um[1 + d] * unm + pm * N[d] + up[1 + d] * unp + pp * N[d]) - h * lam * (up[1 + d] - um[1 + d]);
+  out[4] = h * ((um[4] + pm) * unm + (up[4] + pp) * unp) - h * lam * (up[4] - um[4]);
+}
+
+// Ghost state on a boundary face: tag 1 farfield (given state), tag 2 slip wall
+// (density and energy kept, normal momentum mirrored).
+template <class T>
+__device__ __forceinline__ void ghost_state(int tag, const T um[5], const T N[3], const T far[5], T up[5]) {
+  if (tag == 2) {
+    const T nn2 = N[0] * N[0] + N[1] * N[1] + N[2] * N[2];
+    const T mn = (um[1] * N[0] + um[2] * N[1] + um[3] * N[2]) / nn2;
+    up[0] = um[0];
+    up[1] = um[1] - T(2) * mn * N[0];
+    up[2] = um[2] - T(2) * mn * N[1];
+    up[3] = um[3] - T(2) * mn * N[2];
+    up[4] = um[4];
+  } else {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) up[v] = far[v];
+  }
+}
+
+// Area-weighted outward normal of local face f: N_f = M^T (2 A n)_ref with the
+// reference vectors (1,1,1), (-1,0,0), (0,-1,0), (0,0,-1).
+template <class T>
+__device__ __forceinline__ void face_normal(int f, const double M[9], T N[3]) {
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const double v = f == 0 ? (M[e] + M[3 + e] + M[6 + e]) : -M[3 * (f - 1) + e];
+    N[e] = T(v);
+  }
+}
+
+}  // namespace tetdg

@@ -1,0 +1,105 @@
+// Layout conversion, quadrature-point coordinates and L2 projection kernels.
+#include <hip/hip_runtime.h>
+
+#include "dg_launch.hpp"
+
+namespace tetdg {
+
+namespace {
+
+template <class S>
+__global__ void set_state_kernel(MeshView m, int np, const double* __restrict__ user, S* __restrict__ out) {
+  const int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (n >= m.epad) return;
+  const int64_t src = m.perm[n];
+  for (int v = 0; v < 5; ++v)
+    for (int i = 0; i < np; ++i) out[(int64_t)(v * np + i) * m.epad + n] = S(user[(src * 5 + v) * np + i]);
+}
+
+template <class S>
+__global__ void get_state_kernel(MeshView m, int np, const S* __restrict__ in, double* __restrict__ user) {
+  const int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (n >= m.n_elem) return;
+  const int64_t dst = m.perm[n];
+  for (int v = 0; v < 5; ++v)
+    for (int i = 0; i < np; ++i) user[(dst * 5 + v) * np + i] = double(in[(int64_t)(v * np + i) * m.epad + n]);
+}
+
+__global__ void volume_points_kernel(MeshView m, int nq, RefView r, double* __restrict__ xyz) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= m.n_elem * nq) return;
+  const int64_t n = t / nq;
+  const int q = (int)(t % nq);
+  const int64_t dst = m.perm[n];
+  for (int d = 0; d < 3; ++d) {
+    double x = m.x0j[d * m.epad + n];
+    for (int c = 0; c < 3; ++c) x += m.x0j[(3 + 3 * d + c) * m.epad + n] * r.qx[3 * q + c];
+    xyz[(dst * nq + q) * 3 + d] = x;
+  }
+}
+
+// c_i = (1/|K|) int_K U phi_i = 6 sum_q w_q U(x_q) phi_i(xi_q); one thread per (element, mode)
+template <class S>
+__global__ void project_kernel(MeshView m, int np, int nq, RefView r, double gamma, const double* __restrict__ prim,
+                               S* __restrict__ out) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= m.epad * np) return;
+  const int64_t n = t / np;
+  const int i = (int)(t % np);
+  const int64_t src = m.perm[n];
+  double acc[5] = {0, 0, 0, 0, 0};
+  for (int q = 0; q < nq; ++q) {
+    const double* pq = prim + (src * nq + q) * 5;
+    const double rho = pq[0], u = pq[1], v = pq[2], w = pq[3], p = pq[4];
+    const double U[5] = {rho, rho * u, rho * v, rho * w, p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)};
+    const double wb = 6.0 * r.qw[q] * r.B[q * np + i];
+    for (int c = 0; c < 5; ++c) acc[c] += wb * U[c];
+  }
+  for (int c = 0; c < 5; ++c) out[(int64_t)(c * np + i) * m.epad + n] = S(acc[c]);
+}
+
+inline int np_of(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+hipError_t launch_set_state(int p, int prec, const MeshView& m, const double* user, void* internal, hipStream_t s) {
+  if (prec == 1)
+    hipLaunchKernelGGL(set_state_kernel<float>, dim3(nblocks(m.epad, 256)), dim3(256), 0, s, m, np_of(p), user,
+                       (float*)internal);
+  else
+    hipLaunchKernelGGL(set_state_kernel<double>, dim3(nblocks(m.epad, 256)), dim3(256), 0, s, m, np_of(p), user,
+                       (double*)internal);
+  return hipGetLastError();
+}
+
+hipError_t launch_get_state(int p, int prec, const MeshView& m, const void* internal, double* user, hipStream_t s) {
+  if (prec == 1)
+    hipLaunchKernelGGL(get_state_kernel<float>, dim3(nblocks(m.n_elem, 256)), dim3(256), 0, s, m, np_of(p),
+                       (const float*)internal, user);
+  else
+    hipLaunchKernelGGL(get_state_kernel<double>, dim3(nblocks(m.n_elem, 256)), dim3(256), 0, s, m, np_of(p),
+                       (const double*)internal, user);
+  return hipGetLastError();
+}
+
+hipError_t launch_volume_points(int p, const MeshView& m, const RefView& r, double* xyz, hipStream_t s) {
+  const int nq = (p + 1) * (p + 1) * (p + 1);
+  hipLaunchKernelGGL(volume_points_kernel, dim3(nblocks(m.n_elem * nq, 256)), dim3(256), 0, s, m, nq, r, xyz);
+  return hipGetLastError();
+}
+
+hipError_t launch_project(int p, int prec, const MeshView& m, const RefView& r, double gamma, const double* prim,
+                          void* internal, hipStream_t s) {
+  const int np = np_of(p), nq = (p + 1) * (p + 1) * (p + 1);
+  // padding elements map to caller element 0 (perm), so every row is a valid state
+  if (prec == 1)
+    hipLaunchKernelGGL(project_kernel<float>, dim3(nblocks(m.epad * np, 256)), dim3(256), 0, s, m, np, nq, r, gamma,
+                       prim, (float*)internal);
+  else
+    hipLaunchKernelGGL(project_kernel<double>, dim3(nblocks(m.epad * np, 256)), dim3(256), 0, s, m, np, nq, r, gamma,
+                       prim, (double*)internal);
+  return hipGetLastError();
+}
+
+}  // namespace tetdg

@@ -1,0 +1,179 @@
+"""Python front end of the HIP DG library: torch tensors supply device memory and
+the stream; every computation happens in libtetdg.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from ._lib import check, lib
+
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}
+RENUMBER = {"none": 0, "rcm": 1, "morton": 2, "hilbert": 3}
+
+
+def _ptr(t: torch.Tensor) -> int:
+    return t.data_ptr()
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Solver:
+    """One DG discretisation (order p, precision mode) of one tet mesh on one GPU.
+
+    State tensors returned by this class are in the internal layout
+    [5][N_p][n_elem_pad] (renumbered element order); user-layout tensors are
+    [n_elem][5][N_p] float64 in the caller's element order.
+    """
+
+    def __init__(self, p: int, precision: str = "fp64", gamma: float = 1.4, device: str = "cuda"):
+        self.p = p
+        self.precision = precision
+        self.gamma = gamma
+        self.device = torch.device(device)
+        ctx = ctypes.c_void_p()
+        check(lib.tdg_create(p, PRECISIONS[precision], gamma, ctypes.byref(ctx)), None, "tdg_create")
+        self._ctx = ctx
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        check(lib.tdg_sizes(ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), ctx)
+        self.n_modes, self.n_vol_points, self.n_face_points = a.value, b.value, c.value
+        self.state_dtype = torch.float32 if precision == "fp32" else torch.float64
+        self._mesh_buf = None
+        self.perm = None
+
+    def __del__(self):
+        ctx = getattr(self, "_ctx", None)
+        if ctx is not None and lib is not None:
+            lib.tdg_destroy(ctx)
+            self._ctx = None
+
+    @property
+    def ctx(self):
+        return self._ctx
+
+    # ----------------------------------------------------------------- mesh
+    def upload_mesh(self, elem_vid, elem_xyz, bface_vid=None, bface_tag=None, renumber: str = "rcm",
+                    stream=None) -> np.ndarray:
+        vid = np.ascontiguousarray(elem_vid, dtype=np.int64)
+        xyz = np.ascontiguousarray(elem_xyz, dtype=np.float64)
+        n = vid.shape[0]
+        nb = 0 if bface_vid is None else len(bface_vid)
+        bv = np.ascontiguousarray(bface_vid if nb else np.zeros((0, 3)), dtype=np.int64)
+        bt = np.ascontiguousarray(bface_tag if nb else np.zeros((0,)), dtype=np.int32)
+        perm = np.empty(n, dtype=np.int64)
+        check(lib.tdg_mesh_upload(self._ctx, n, vid.ctypes.data, xyz.ctypes.data, nb,
+                                  bv.ctypes.data if nb else None, bt.ctypes.data if nb else None,
+                                  RENUMBER[renumber], perm.ctypes.data), self._ctx, "tdg_mesh_upload")
+        self.perm = perm
+        self.n_elem = n
+        size = ctypes.c_size_t()
+        check(lib.tdg_mesh_device_bytes(self._ctx, ctypes.byref(size)), self._ctx)
+        # over-allocate by 256 bytes and bind an aligned view
+        raw = torch.empty(size.value + 256, dtype=torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        self._mesh_buf = raw
+        check(lib.tdg_mesh_bind(self._ctx, ctypes.c_void_p(raw.data_ptr() + off), size.value, _stream(stream)),
+              self._ctx, "tdg_mesh_bind")
+        epad = ctypes.c_int64()
+        check(lib.tdg_state_elems(self._ctx, ctypes.byref(epad)), self._ctx)
+        self.n_elem_pad = epad.value
+        return perm
+
+    def upload(self, mesh, renumber: str = "rcm", stream=None) -> np.ndarray:
+        """Upload a synthetic.TetMesh."""
+        return self.upload_mesh(mesh.elem_vid, mesh.elem_xyz, mesh.bface_vid, mesh.bface_tag, renumber, stream)
+
+    def set_farfield(self, prim) -> None:
+        arr = np.ascontiguousarray(prim, dtype=np.float64)
+        check(lib.tdg_set_farfield(self._ctx, arr.ctypes.data), self._ctx)
+
+    def mesh_stats(self) -> dict:
+        out = np.zeros(6, dtype=np.int64)
+        check(lib.tdg_mesh_stats(self._ctx, out.ctypes.data), self._ctx)
+        keys = ["n_elem", "n_elem_pad", "interior_faces", "boundary_faces", "bandwidth", "near64"]
+        return dict(zip(keys, out.tolist()))
+
+    # ----------------------------------------------------------------- state
+    def new_state(self) -> torch.Tensor:
+        return torch.zeros((5, self.n_modes, self.n_elem_pad), dtype=self.state_dtype, device=self.device)
+
+    def set_state(self, U_user: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        assert U_user.dtype == torch.float64 and U_user.is_contiguous()
+        assert tuple(U_user.shape) == (self.n_elem, 5, self.n_modes)
+        out = self.new_state() if out is None else out
+        check(lib.tdg_set_state(self._ctx, _ptr(U_user), _ptr(out), _stream(stream)), self._ctx, "tdg_set_state")
+        return out
+
+    def get_state(self, U_int: torch.Tensor, stream=None) -> torch.Tensor:
+        self._check_state(U_int)
+        out = torch.empty((self.n_elem, 5, self.n_modes), dtype=torch.float64, device=self.device)
+        check(lib.tdg_get_state(self._ctx, _ptr(U_int), _ptr(out), _stream(stream)), self._ctx, "tdg_get_state")
+        return out
+
+    def volume_points(self, stream=None) -> torch.Tensor:
+        out = torch.empty((self.n_elem, self.n_vol_points, 3), dtype=torch.float64, device=self.device)
+        check(lib.tdg_volume_points(self._ctx, _ptr(out), _stream(stream)), self._ctx, "tdg_volume_points")
+        return out
+
+    def project(self, prim: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        assert prim.dtype == torch.float64 and prim.is_contiguous()
+        assert tuple(prim.shape) == (self.n_elem, self.n_vol_points, 5)
+        out = self.new_state() if out is None else out
+        check(lib.tdg_project(self._ctx, _ptr(prim), _ptr(out), _stream(stream)), self._ctx, "tdg_project")
+        return out
+
+    def project_fn(self, prim_fn, stream=None) -> torch.Tensor:
+        """Evaluate an analytic primitive field at the volume points and project it."""
+        x = self.volume_points(stream)
+        return self.project(prim_fn(x).contiguous(), stream=stream)
+
+    # ----------------------------------------------------------------- hot path
+    def _check_state(self, U: torch.Tensor) -> None:
+        assert U.device.type == "cuda" and U.dtype == self.state_dtype and U.is_contiguous()
+        assert tuple(U.shape) == (5, self.n_modes, self.n_elem_pad)
+
+    def residual(self, U: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        self._check_state(U)
+        out = self.new_state() if out is None else out
+        self._check_state(out)
+        check(lib.tdg_residual(self._ctx, _ptr(U), _ptr(out), _stream(stream)), self._ctx, "tdg_residual")
+        return out
+
+    def new_work(self) -> torch.Tensor:
+        return torch.empty((2, 5, self.n_modes, self.n_elem_pad), dtype=self.state_dtype, device=self.device)
+
+    def rk_step(self, U: torch.Tensor, dt: float, n_steps: int = 1, work: torch.Tensor | None = None,
+                stream=None) -> torch.Tensor:
+        """n SSP-RK3 steps in place on U (internal layout)."""
+        self._check_state(U)
+        work = self.new_work() if work is None else work
+        assert work.dtype == self.state_dtype and work.numel() >= 2 * U.numel()
+        check(lib.tdg_rk_step(self._ctx, _ptr(U), _ptr(work), float(dt), int(n_steps), _stream(stream)),
+              self._ctx, "tdg_rk_step")
+        return U
+
+    def residual_vjp(self, U: torch.Tensor, W: torch.Tensor, out: torch.Tensor | None = None,
+                     stream=None) -> torch.Tensor:
+        self._check_state(U)
+        self._check_state(W)
+        out = self.new_state() if out is None else out
+        check(lib.tdg_residual_vjp(self._ctx, _ptr(U), _ptr(W), _ptr(out), _stream(stream)), self._ctx,
+              "tdg_residual_vjp")
+        return out
+
+    def sync(self, stream=None) -> None:
+        check(lib.tdg_sync_check(self._ctx, _stream(stream)), self._ctx, "tdg_sync_check")
+
+
+def debug_tables(p: int, which: int) -> np.ndarray:
+    """Reference tables computed by the library on the host (see tdg_debug_tables)."""
+    need = ctypes.c_size_t()
+    check(lib.tdg_debug_tables(p, which, None, 0, ctypes.byref(need)))
+    out = np.empty(need.value, dtype=np.float64)
+    check(lib.tdg_debug_tables(p, which, out.ctypes.data, need.value, ctypes.byref(need)))
+    return out

@@ -1,0 +1,55 @@
+"""Helpers for the GPU tests (imported only by tests marked gpu)."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from oracle.dg import DG
+from synthetic import fields, kuhn_cube
+
+
+def make_mesh(kind: str):
+    if kind == "ragged":      # 5 x 4 x 3 hexes: 360 tets, not a multiple of 16
+        return kuhn_cube((5, 4, 3), length=1.0, jitter=0.2, shuffle_seed=2209, vid_seed=2210)
+    if kind == "jitter4":
+        return kuhn_cube(4, jitter=0.2, shuffle_seed=2209, vid_seed=2210)
+    if kind == "bump":        # farfield x/y sides, slip wall with bump on y = 0, periodic z
+        return kuhn_cube(4, periodic=(False, False, True), jitter=0.2, bump_height=0.05,
+                         shuffle_seed=2209, vid_seed=2210)
+    if kind == "c1":
+        return kuhn_cube(4)
+    raise ValueError(kind)
+
+
+def solver(p, prec, mesh, renumber="hilbert", farfield=None):
+    from paper_2209_01877_amd import Solver
+
+    s = Solver(p, prec)
+    s.upload(mesh, renumber=renumber)
+    if farfield is not None:
+        s.set_farfield(farfield)
+    return s
+
+
+def oracle(p, mesh, farfield=(1.0, 0.5 * np.sqrt(1.4), 0.0, 0.0, 1.0)):
+    return DG(p, mesh.elem_vid, mesh.elem_xyz, mesh.bface_vid, mesh.bface_tag, farfield_prim=farfield)
+
+
+def random_state(dg, seed=7, scale=0.01):
+    return torch.from_numpy(fields.random_coefficients(dg.n_elem, dg.Np, seed=seed, scale=scale))
+
+
+def gpu_residual(s, U_user: torch.Tensor) -> torch.Tensor:
+    Ui = s.set_state(U_user.cuda().contiguous())
+    R = s.get_state(s.residual(Ui)).cpu()
+    s.sync()
+    return R
+
+
+def rel_err(dg, a, b) -> float:
+    """Largest per-variable normwise relative L2 error (function-space norm); a variable
+    whose reference is identically zero is measured in absolute terms."""
+    num = dg.l2_norm(a - b)
+    den = dg.l2_norm(b)
+    den = torch.where(den > 0, den, torch.ones_like(den))
+    return float((num / den).max())

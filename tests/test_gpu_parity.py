@@ -1,0 +1,137 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Bars: FP64 1e-12 and FP32 1e-5 in the per-variable normwise relative L2 norm
+(function-space norm, sum_K |K| sum_i c^2); mixed bf16/fp16 report their error and
+are held to a loose sanity bound (their accuracy is a measured quantity).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from synthetic import fields
+
+pytestmark = pytest.mark.gpu
+
+from gpu_common import gpu_residual, make_mesh, oracle, random_state, rel_err, solver  # noqa: E402
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5, "bf16": 5e-2, "fp16": 1e-2}
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16", "fp16"])
+def test_residual_random_state(p, prec):
+    mesh = make_mesh("ragged")
+    dg = oracle(p, mesh)
+    U = random_state(dg)
+    R_ref = dg.residual(U)
+    R = gpu_residual(solver(p, prec, mesh), U)
+    err = rel_err(dg, R, R_ref)
+    print(f"p={p} {prec} residual rel L2 error {err:.3e}")
+    assert err < TOL[prec]
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_residual_with_boundaries(p, prec):
+    far = (1.0, 0.5 * math.sqrt(1.4), 0.0, 0.0, 1.0)
+    mesh = make_mesh("bump")
+    dg = oracle(p, mesh, far)
+    U = random_state(dg, seed=3)
+    R_ref = dg.residual(U)
+    R = gpu_residual(solver(p, prec, mesh, farfield=far), U)
+    err = rel_err(dg, R, R_ref)
+    print(f"p={p} {prec} boundary residual rel L2 error {err:.3e}")
+    assert err < TOL[prec]
+
+
+@pytest.mark.parametrize("p", [1, 3])
+def test_points_and_projection(p):
+    mesh = make_mesh("jitter4")
+    dg = oracle(p, mesh)
+    s = solver(p, "fp64", mesh)
+    x = s.volume_points().cpu().numpy()
+    assert np.abs(x - dg.volume_points()).max() < 1e-14
+    vortex = lambda z: fields.isentropic_vortex(z, length=1.0, beta=0.5)  # noqa: E731
+    U_ref = dg.project(vortex)
+    U = s.get_state(s.project_fn(vortex)).cpu()
+    assert rel_err(dg, U, U_ref) < 1e-14
+
+
+def test_c1_ten_rk_steps():
+    """P1 density wave on the periodic 4^3 x 6 cube, 10 SSP-RK3 steps at CFL 0.2, FP64."""
+    mesh = make_mesh("c1")
+    dg = oracle(1, mesh)
+    U_ref = dg.project(lambda z: fields.sine_wave(z))
+    dt = dg.stable_dt(U_ref, cfl=0.2)
+    s = solver(1, "fp64", mesh, renumber="rcm")
+    Ui = s.project_fn(lambda z: fields.sine_wave(z))
+    U0 = s.get_state(Ui).cpu()
+    assert rel_err(dg, U0, U_ref) < 1e-14
+    for _ in range(10):
+        U_ref = dg.rk3_step(U_ref, dt)
+    s.rk_step(Ui, dt, 10)
+    U = s.get_state(Ui).cpu()
+    s.sync()
+    err = rel_err(dg, U - U0, U_ref - U0)
+    print(f"C1: 10 steps dt={dt:.4e}, increment rel L2 error {err:.3e}")
+    assert err < 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_rk_step_random_state(prec):
+    mesh = make_mesh("ragged")
+    p = 2
+    dg = oracle(p, mesh)
+    U = random_state(dg, seed=5)
+    dt = 0.5 * dg.stable_dt(U)
+    U_ref = U
+    for _ in range(3):
+        U_ref = dg.rk3_step(U_ref, dt)
+    s = solver(p, prec, mesh)
+    Ui = s.set_state(U.cuda())
+    s.rk_step(Ui, dt, 3)
+    Ug = s.get_state(Ui).cpu()
+    s.sync()
+    err = rel_err(dg, Ug - U, U_ref - U)
+    assert err < TOL[prec] * (10 if prec == "fp32" else 1)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16", "fp16"])
+def test_renumbering_invariance(prec):
+    """Results in the caller's order do not depend on the internal numbering."""
+    mesh = make_mesh("jitter4")
+    dg = oracle(2, mesh)
+    U = random_state(dg, seed=9)
+    outs = [gpu_residual(solver(2, prec, mesh, renumber=r), U) for r in ["none", "rcm", "morton", "hilbert"]]
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16", "fp16"])
+def test_free_stream_and_conservation(prec):
+    mesh = make_mesh("jitter4")
+    p = 3
+    dg = oracle(p, mesh)
+    s = solver(p, prec, mesh)
+    U = s.project_fn(lambda z: fields.freestream(z, 1.0, (0.3, -0.2, 0.5), 1.0))
+    R = s.get_state(s.residual(U)).cpu()
+    bound = {"fp64": 1e-11, "fp32": 1e-4, "bf16": 1e-11, "fp16": 1e-11}[prec]
+    assert R.abs().max().item() < bound, R.abs().max().item()
+    Ur = random_state(dg, seed=11)
+    R = gpu_residual(s, Ur)
+    total = (dg.volume[:, None] * R[:, :, 0]).sum(0)
+    scale = (dg.volume[:, None] * R[:, :, 0].abs()).sum(0)
+    ctol = {"fp64": 1e-13, "fp32": 1e-6, "bf16": 1e-6, "fp16": 1e-6}[prec]
+    assert (total.abs() <= ctol * scale).all(), (total, scale)
+
+
+def test_deterministic():
+    mesh = make_mesh("ragged")
+    dg = oracle(3, mesh)
+    U = random_state(dg)
+    s = solver(3, "fp64", mesh)
+    a = gpu_residual(s, U)
+    b = gpu_residual(s, U)
+    assert torch.equal(a, b)
