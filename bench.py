@@ -104,10 +104,72 @@ def run_gpu(args):
     if "fp64" in states:
         ref = states["fp64"]
         for prec, U in states.items():
-            diff = (U - ref).pow(2).sum(dim=(0, 2)).sqrt()
-            norm = ref.pow(2).sum(dim=(0, 2)).sqrt()
-            results[prec]["rel_l2_vs_fp64"] = (diff / torch.where(norm > 0, norm, torch.ones_like(norm))).tolist()
+            results[prec].update(l2_errors(U, ref))
     return mesh, dt, results
+
+
+def l2_errors(U, ref):
+    """Relative L2 difference of coefficient arrays (E, 5, N_p): over all variables, and per
+    variable relative to the norm of the whole state (the vortex has w = 0 identically)."""
+    diff = (U - ref).pow(2).sum(dim=(0, 2)).sqrt()
+    total = ref.pow(2).sum().sqrt()
+    return {"rel_l2_vs_fp64": float((U - ref).pow(2).sum().sqrt() / total),
+            "rel_l2_vs_fp64_per_var": (diff / total).tolist()}
+
+
+def run_p4(args):
+    """P4 (35 modes) vortex on 40^3 x 6 tets: mixed vs fp32 GDOF/s per stage and error vs fp64."""
+    from paper_2209_01877_amd import Solver
+
+    mesh = kuhn_cube(40, length=10.0, shuffle_seed=2209, vid_seed=2210)
+    p = 4
+    dt = 0.2 * 0.41 * (10.0 / 40) / ((2 * p + 1) * 3.1)
+    vortex = lambda x: fields.isentropic_vortex(x, length=10.0, beta=5.0, mach=0.5)  # noqa: E731
+    out, states = {}, {}
+    for prec in ["bf16", "fp32", "fp64"]:
+        s = Solver(p, prec)
+        s.upload(mesh, renumber=args.renumber)
+        U = s.project_fn(vortex)
+        work = s.new_work()
+        U0 = U.clone()
+        t = timed(lambda: s.rk_step(U, dt, 1, work), args.steps, args.warmup)
+        U.copy_(U0)
+        s.rk_step(U, dt, args.steps, work)
+        states[prec] = s.get_state(U)
+        s.sync()
+        out[prec] = {"gdof_per_s_per_stage": mesh.n_elem * s.n_modes * 5 * 3 * args.steps / t / 1e9,
+                     "ms_per_step": 1e3 * t / args.steps}
+        del s, U, U0, work
+        torch.cuda.empty_cache()
+    for prec in out:
+        out[prec].update(l2_errors(states[prec], states["fp64"]))
+    out["workload"] = f"isentropic vortex, P4, periodic 40^3 x 6 ({mesh.n_elem} tets), {args.steps} SSP-RK3 steps"
+    return out
+
+
+def run_adjoint(args):
+    """Differentiation form: P2 on the jittered 40^3 x 6 cube; time of the residual VJP over
+    the time of the residual (fp64 and fp32)."""
+    from paper_2209_01877_amd import Solver
+
+    mesh = kuhn_cube(40, jitter=0.2, jitter_seed=1877, shuffle_seed=2209)
+    out = {}
+    for prec in ["fp64", "fp32"]:
+        s = Solver(2, prec)
+        s.upload(mesh, renumber=args.renumber)
+        U = s.project_fn(fields.RandomSmooth(42))
+        W = torch.randn(U.shape, dtype=U.dtype, device=U.device, generator=torch.Generator(device="cuda").manual_seed(43))
+        R = s.new_state()
+        Ub = s.new_state()
+        tf = timed(lambda: s.residual(U, R), args.steps, args.warmup)
+        tb = timed(lambda: s.residual_vjp(U, W, Ub), args.steps, args.warmup)
+        s.sync()
+        out[prec] = {"residual_ms": 1e3 * tf / args.steps, "vjp_ms": 1e3 * tb / args.steps,
+                     "adjoint_over_forward": tb / tf}
+        del s, U, W, R, Ub
+        torch.cuda.empty_cache()
+    out["workload"] = f"P2, jittered 40^3 x 6 ({mesh.n_elem} tets), RandomSmooth(42) state, Gaussian cotangent"
+    return out
 
 
 def cpu_baseline(p: int, n_cpu: int, steps: int):
@@ -146,6 +208,7 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=16)
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the P4 and adjoint workloads")
     args = ap.parse_args()
     args.precisions = args.precisions.split(",")
     if args.gpus != 1:
@@ -194,6 +257,10 @@ def main():
     }
     if "fp32" in res and head != "fp32":
         line["speedup_vs_fp32"] = r["gdof_per_s_per_stage"] / res["fp32"]["gdof_per_s_per_stage"]
+    if not args.no_extra:
+        line["p4_precision_form"] = run_p4(args)
+        line["adjoint"] = run_adjoint(args)
+        line["adjoint_over_forward_fp64"] = line["adjoint"]["fp64"]["adjoint_over_forward"]
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args.p, args.cpu_n, args.cpu_steps)
     print(json.dumps(line), flush=True)

@@ -31,7 +31,9 @@
  *   - Compute calls are asynchronous on the given hipStream_t (passed as void*,
  *     NULL = the null stream).  Kernel-side faults surface on the next
  *     synchronisation; tdg_sync_check() synchronises and reports them.
- *   - The library allocates no device memory after tdg_mesh_bind().
+ *   - The library allocates no device memory after tdg_mesh_bind().  The mixed modes keep a
+ *     scratch operand companion inside the bound mesh buffer, so calls on one context must
+ *     not overlap in time (on different streams).
  *   - A context is not thread-safe; distinct contexts are independent.
  *   - U, R, W and Ubar must not alias, except U in tdg_rk_step (updated in place).
  */
@@ -155,8 +157,13 @@ int tdg_residual(tdg_ctx* ctx, const void* U, void* R, void* hip_stream);
 
 /* n_steps SSP-RK3 steps of size dt on U (internal, in place):
  *   U1 = U + dt R(U);  U2 = 3/4 U + 1/4 (U1 + dt R(U1));  U <- 1/3 U + 2/3 (U2 + dt R(U2)).
- * work: device, two internal states.  One fused residual+update launch per stage. */
+ * work: device buffer of tdg_work_bytes() bytes (two internal states, plus in the mixed
+ * modes three low-precision operand companions).  One fused residual+update launch per
+ * stage (mixed modes: plus one companion pass over U per call). */
 int tdg_rk_step(tdg_ctx* ctx, void* U, void* work, double dt, int n_steps, void* hip_stream);
+
+/* Bytes of the work buffer tdg_rk_step needs. */
+int tdg_work_bytes(const tdg_ctx* ctx, size_t* bytes);
 
 /* Vector-Jacobian product Ubar = (dR/dU)^T W at U (all internal layout; Ubar overwritten).
  * Element-centric: each element gathers U and W of its neighbours and applies the
@@ -165,6 +172,26 @@ int tdg_rk_step(tdg_ctx* ctx, void* U, void* work, double dt, int n_steps, void*
  * the adjoint in FP64.  At exact ties of max(lambda-, lambda+) the derivative is split
  * evenly, and d|x|/dx = 0 at x = 0. */
 int tdg_residual_vjp(tdg_ctx* ctx, const void* U, const void* W, void* Ubar, void* hip_stream);
+
+/* One SSP-RK3 stage: U_out = alpha U0 + (1 - alpha)(U_in + dt R(U_in)) (internal states;
+ * U0 may be NULL when alpha == 0; U_out may alias U0 but not U_in).  The same fused
+ * kernel as tdg_rk_step; exposed so an adjoint can recompute stage states. */
+int tdg_rk_stage(tdg_ctx* ctx, const void* U_in, const void* U0, void* U_out, double alpha, double dt,
+                 void* hip_stream);
+
+/* Accumulating VJP: Out = c (dR/dU)^T(U) W + sum_{k < n_terms} a[k] Y[k], all internal
+ * states (Y[k] may alias W; Out must not alias U, W or any Y[k]).  n_terms in 0..3.
+ * This is the per-stage operation of the discrete SSP-RK3 adjoint (reverse step):
+ *   Ub2 = (2/3) dt J(U2)^T Ub3 + (2/3) Ub3;   Ub1 = (1/4) dt J(U1)^T Ub2 + (1/4) Ub2;
+ *   Ub0 = dt J(U0)^T Ub1 + Ub1 + (3/4) Ub2 + (1/3) Ub3. */
+int tdg_residual_vjp_axpy(tdg_ctx* ctx, const void* U, const void* W, double c, int n_terms, const void* const* Y,
+                          const double* a, void* Out, void* hip_stream);
+
+/* Integrated slip-wall pressure J = sum over slip-wall faces of int_f p(U-) dA (boundary-face
+ * quadrature of eq. 11) at internal state U, and optionally dJ/dU (internal layout, overwritten;
+ * NULL to skip).  J: device double, overwritten.  The objective of the full configuration's
+ * adjoint (its gradient seeds the trajectory adjoint). */
+int tdg_wall_pressure(tdg_ctx* ctx, const void* U, double* J, void* dJdU, void* hip_stream);
 
 /* Synchronise the stream; map a pending asynchronous HIP error to TDG_ERR_HIP. */
 int tdg_sync_check(tdg_ctx* ctx, void* hip_stream);

@@ -139,6 +139,17 @@ class DG:
         vol = self.volume if elems is None else self.volume[elems]
         return (self.volume_term(U, elems) - self.face_term(U, elems)) / vol[:, None, None]
 
+    def wall_pressure(self, U: torch.Tensor) -> torch.Tensor:
+        """Integrated slip-wall pressure, sum over wall faces of 2 A_f sum_q w_q p(U-_q).
+
+        The objective of the full configuration's adjoint (a boundary-face integral of the
+        kind in eq. 11); dJ/dU follows by autograd."""
+        wall = torch.nonzero(self.f_tag == 2).flatten()
+        em, fm = self.f_em[wall], self.f_fm[wall]
+        Um = torch.einsum("fqi,fvi->fqv", self.Bf[fm], U[em])
+        p = euler.pressure(Um, self.gamma)
+        return (2.0 * self.f_area[wall][:, None] * self.wf[None, :] * p).sum()
+
     # ------------------------------------------------------------------ time
     def rk3_step(self, U: torch.Tensor, dt: float, rhs=None) -> torch.Tensor:
         """One SSP-RK3 (Shu-Osher) step: U_out = a U0 + (1-a)(U_in + dt R(U_in)), a = 0, 3/4, 1/3."""

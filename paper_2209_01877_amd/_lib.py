@@ -43,6 +43,10 @@ _SIGS = {
     "tdg_residual": (_i, [_p, _p, _p, _p]),
     "tdg_rk_step": (_i, [_p, _p, _p, _d, _i, _p]),
     "tdg_residual_vjp": (_i, [_p, _p, _p, _p, _p]),
+    "tdg_work_bytes": (_i, [_p, ctypes.POINTER(_sz)]),
+    "tdg_rk_stage": (_i, [_p, _p, _p, _p, _d, _d, _p]),
+    "tdg_residual_vjp_axpy": (_i, [_p, _p, _p, _d, _i, _p, _p, _p, _p]),
+    "tdg_wall_pressure": (_i, [_p, _p, _p, _p, _p]),
     "tdg_sync_check": (_i, [_p, _p]),
     "tdg_debug_tables": (_i, [_i, _i, _p, _sz, ctypes.POINTER(_sz)]),
 }

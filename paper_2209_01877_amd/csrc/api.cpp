@@ -29,12 +29,12 @@ struct tdg_ctx {
   std::vector<double> M, inv_vol, x0j;
   std::vector<int32_t> nbr, fcode, perm;
   std::vector<unsigned char> stage_tab, vjp_tab;
-  std::vector<double> mom;
+  std::vector<double> mom, mean_tab;
   // device buffer (caller-owned) and offsets into it
   char* dev = nullptr;
   size_t dev_bytes = 0;
   size_t off_M = 0, off_iv = 0, off_x0j = 0, off_nbr = 0, off_fcode = 0, off_perm = 0, off_stab = 0, off_vtab = 0,
-         off_mom = 0, off_qx = 0, off_qw = 0, off_B = 0, total = 0;
+         off_mom = 0, off_mtab = 0, off_qx = 0, off_qw = 0, off_B = 0, off_fw = 0, off_Bf = 0, off_comp = 0, total = 0;
   double far[5] = {1.0, 0.0, 0.0, 0.0, 2.5};
 };
 
@@ -167,6 +167,20 @@ void pack_vjp(const RefElem& R, int prec, std::vector<unsigned char>& out) {
   auto slot = [&](auto&& A) {
     for (int l = 0; l < 64; ++l) put(out, f64 ? TDG_FP64 : TDG_FP32, A(l % 16, l / 16));
   };
+  // interp(qt, s) and trace(f, ft, s): the forward interpolation tables
+  for (int qt = 0; qt < O::QT; ++qt)
+    for (int s = 0; s < V::KS; ++s)
+      slot([&](int r, int g) {
+        const int q = 16 * qt + r, mode = 4 * s + g;
+        return (q < NQ && mode < NP) ? R.B[(size_t)q * NP + mode] : 0.0;
+      });
+  for (int f = 0; f < 4; ++f)
+    for (int ft = 0; ft < O::FT; ++ft)
+      for (int s = 0; s < V::KS; ++s)
+        slot([&](int r, int g) {
+          const int q = 16 * ft + r, mode = 4 * s + g;
+          return (q < NF && mode < NP) ? R.Bf[((size_t)f * NF + q) * NP + mode] : 0.0;
+        });
   // tinterp(qt, d, s): rows = points, k = modes: w_q dphi/dxi_d
   for (int qt = 0; qt < O::QT; ++qt)
     for (int d = 0; d < 3; ++d)
@@ -224,6 +238,24 @@ void build_tables(tdg_ctx* c) {
     for (int f = 0; f < 4; ++f)
       for (int q = 0; q < NF; ++q) c->mom[(3 + f) * NP + i] += c->ref.fw[q] * c->ref.Bf[((size_t)f * NF + q) * NP + i];
   }
+  // mean-flux projection as fp64 MFMA A operands: slot (mt, step), lane l holds A[r][k] with
+  // r = l % 16, k = 4 step + l / 16; the row r = g + 4 j holds mode 16 mt + 4 g + j so that the
+  // fp64 accumulator element j of lane group g is the same mode as in the fp32 accumulators.
+  // k = 0..2: volume moments (+); k = 3: face 0; k = 4..6: faces 1..3 (face moments negated).
+  const int MT = (NP + 15) / 16;
+  c->mean_tab.assign((size_t)MT * 2 * 64, 0.0);
+  for (int mt = 0; mt < MT; ++mt)
+    for (int step = 0; step < 2; ++step)
+      for (int l = 0; l < 64; ++l) {
+        const int r = l % 16, k = 4 * step + l / 16;
+        const int mode = 16 * mt + 4 * (r % 4) + r / 4;
+        double v = 0.0;
+        if (mode < NP && k < 7) {
+          const int face = k == 3 ? 0 : k - 3;
+          v = k < 3 ? c->mom[k * NP + mode] : -c->mom[(3 + face) * NP + mode];
+        }
+        c->mean_tab[((size_t)mt * 2 + step) * 64 + l] = v;
+      }
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -246,6 +278,8 @@ RefView refview(const tdg_ctx* c) {
   r.qx = (const double*)(c->dev + c->off_qx);
   r.qw = (const double*)(c->dev + c->off_qw);
   r.B = (const double*)(c->dev + c->off_B);
+  r.fw = (const double*)(c->dev + c->off_fw);
+  r.Bf = (const double*)(c->dev + c->off_Bf);
   return r;
 }
 
@@ -259,6 +293,19 @@ int require_bound(tdg_ctx* c) {
 size_t state_bytes(const tdg_ctx* c) {
   return (size_t)5 * c->ref.np * c->epad * (c->prec == TDG_FP32 ? sizeof(float) : sizeof(double));
 }
+
+bool is_mixed(const tdg_ctx* c) { return c->prec >= TDG_MIXED_BF16; }
+
+size_t comp_bytes(const tdg_ctx* c) { return is_mixed(c) ? companion_bytes(c->p, c->epad) : 0; }
+
+// Companion (q, c0) pointers inside a buffer of companion_bytes().
+void comp_ptrs(const tdg_ctx* c, char* base, void** q, float** c0) {
+  const size_t qb = ((size_t)c->epad * 5 * 32 * ((c->ref.np + 31) / 32) * 2 + 255) & ~(size_t)255;
+  *q = base;
+  *c0 = (float*)(base + qb);
+}
+
+size_t work_bytes(const tdg_ctx* c) { return 2 * state_bytes(c) + 3 * comp_bytes(c); }
 
 }  // namespace
 
@@ -382,9 +429,14 @@ int tdg_mesh_upload(tdg_ctx* c, int64_t n_elem, const int64_t* elem_vid, const d
     c->off_stab = take(c->stage_tab.size());
     c->off_vtab = take(c->vjp_tab.size());
     c->off_mom = take(c->mom.size() * sizeof(double));
+    c->off_mtab = take(c->mean_tab.size() * sizeof(double));
     c->off_qx = take(c->ref.qx.size() * sizeof(double));
     c->off_qw = take(c->ref.qw.size() * sizeof(double));
     c->off_B = take(c->ref.B.size() * sizeof(double));
+    c->off_fw = take(c->ref.fw.size() * sizeof(double));
+    c->off_Bf = take(c->ref.Bf.size() * sizeof(double));
+    // mixed modes: scratch operand companion for single residual / stage calls
+    c->off_comp = take(c->prec >= TDG_MIXED_BF16 ? companion_bytes(c->p, epad) : 0);
     c->total = off;
     c->has_mesh = true;
     c->bound = false;
@@ -423,9 +475,12 @@ int tdg_mesh_bind(tdg_ctx* c, void* dev_buf, size_t bytes, void* hip_stream) {
       {c->off_stab, c->stage_tab.data(), c->stage_tab.size()},
       {c->off_vtab, c->vjp_tab.data(), c->vjp_tab.size()},
       {c->off_mom, c->mom.data(), c->mom.size() * sizeof(double)},
+      {c->off_mtab, c->mean_tab.data(), c->mean_tab.size() * sizeof(double)},
       {c->off_qx, c->ref.qx.data(), c->ref.qx.size() * sizeof(double)},
       {c->off_qw, c->ref.qw.data(), c->ref.qw.size() * sizeof(double)},
       {c->off_B, c->ref.B.data(), c->ref.B.size() * sizeof(double)},
+      {c->off_fw, c->ref.fw.data(), c->ref.fw.size() * sizeof(double)},
+      {c->off_Bf, c->ref.Bf.data(), c->ref.Bf.size() * sizeof(double)},
   };
   for (const Piece& pc : pieces) {
     if (pc.n == 0) continue;
@@ -516,9 +571,27 @@ static StageArgs stage_args(const tdg_ctx* c) {
   a.mesh = view(c);
   a.tab = c->dev + c->off_stab;
   a.mom = (const double*)(c->dev + c->off_mom);
+  a.mean_tab = (const double*)(c->dev + c->off_mtab);
   a.gamma = c->gamma;
   for (int v = 0; v < 5; ++v) a.far[v] = c->far[v];
   return a;
+}
+
+// Mixed modes: build the operand companion of U in the context's scratch area.
+static hipError_t pack_scratch(tdg_ctx* c, const void* U, StageArgs& a, hipStream_t s) {
+  void* q;
+  float* c0;
+  comp_ptrs(c, c->dev + c->off_comp, &q, &c0);
+  a.q_in = q;
+  a.c0_in = c0;
+  return launch_pack(c->p, c->prec, view(c), U, q, c0, s);
+}
+
+int tdg_work_bytes(const tdg_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return TDG_ERR_INVALID_ARG;
+  if (!c->has_mesh) return TDG_ERR_STATE;
+  *bytes = work_bytes(c);
+  return TDG_OK;
 }
 
 int tdg_residual(tdg_ctx* c, const void* U, void* R, void* s) {
@@ -526,6 +599,10 @@ int tdg_residual(tdg_ctx* c, const void* U, void* R, void* s) {
   if (st) return st;
   if (!U || !R || U == R) return fail(c, TDG_ERR_INVALID_ARG, "U and R must be distinct device arrays");
   StageArgs a = stage_args(c);
+  if (is_mixed(c)) {
+    hipError_t e = pack_scratch(c, U, a, (hipStream_t)s);
+    if (e != hipSuccess) return hip_fail(c, e, "pack launch");
+  }
   a.u_in = U;
   a.u0 = U;
   a.u_out = R;
@@ -542,6 +619,16 @@ int tdg_rk_step(tdg_ctx* c, void* U, void* work, double dt, int n_steps, void* s
   char* w = (char*)work;
   void* U1 = w;
   void* U2 = w + state_bytes(c);
+  // mixed: operand companions of U, U1, U2 follow the two states
+  void* q[3] = {nullptr, nullptr, nullptr};
+  float* c0[3] = {nullptr, nullptr, nullptr};
+  if (is_mixed(c)) {
+    for (int k = 0; k < 3; ++k) comp_ptrs(c, w + 2 * state_bytes(c) + k * comp_bytes(c), &q[k], &c0[k]);
+    if (n_steps > 0) {
+      hipError_t e = launch_pack(c->p, c->prec, view(c), U, q[0], c0[0], (hipStream_t)s);
+      if (e != hipSuccess) return hip_fail(c, e, "pack launch");
+    }
+  }
   StageArgs a = stage_args(c);
   a.rk = 1;
   a.dt = dt;
@@ -550,16 +637,68 @@ int tdg_rk_step(tdg_ctx* c, void* U, void* work, double dt, int n_steps, void* s
     const void* base[3] = {nullptr, U, U};
     void* outs[3] = {U1, U2, U};
     const double alphas[3] = {0.0, 0.75, 1.0 / 3.0};
+    const int qin[3] = {0, 1, 2}, qout[3] = {1, 2, 0};
     for (int stg = 0; stg < 3; ++stg) {
       a.u_in = ins[stg];
       a.u0 = base[stg];
       a.u_out = outs[stg];
       a.alpha = alphas[stg];
+      a.q_in = q[qin[stg]];
+      a.c0_in = c0[qin[stg]];
+      a.q_out = q[qout[stg]];
+      a.c0_out = c0[qout[stg]];
       hipError_t e = launch_stage(c->p, c->prec, a, (hipStream_t)s);
       if (e != hipSuccess) return hip_fail(c, e, "rk stage launch");
     }
   }
   return TDG_OK;
+}
+
+int tdg_rk_stage(tdg_ctx* c, const void* U_in, const void* U0, void* U_out, double alpha, double dt, void* s) {
+  int st = require_bound(c);
+  if (st) return st;
+  if (!U_in || !U_out || U_in == U_out || (alpha != 0.0 && !U0))
+    return fail(c, TDG_ERR_INVALID_ARG, "bad stage arrays (U_out must differ from U_in; U0 needed when alpha != 0)");
+  if (!std::isfinite(dt) || !std::isfinite(alpha)) return fail(c, TDG_ERR_INVALID_ARG, "bad dt or alpha");
+  StageArgs a = stage_args(c);
+  if (is_mixed(c)) {
+    hipError_t e = pack_scratch(c, U_in, a, (hipStream_t)s);
+    if (e != hipSuccess) return hip_fail(c, e, "pack launch");
+  }
+  a.rk = 1;
+  a.dt = dt;
+  a.alpha = alpha;
+  a.u_in = U_in;
+  a.u0 = U0;
+  a.u_out = U_out;
+  hipError_t e = launch_stage(c->p, c->prec, a, (hipStream_t)s);
+  return e == hipSuccess ? TDG_OK : hip_fail(c, e, "rk stage launch");
+}
+
+int tdg_residual_vjp_axpy(tdg_ctx* c, const void* U, const void* W, double cw, int n_terms, const void* const* Y,
+                          const double* ya, void* Out, void* s) {
+  int st = require_bound(c);
+  if (st) return st;
+  if (!U || !W || !Out || Out == U || Out == W) return fail(c, TDG_ERR_INVALID_ARG, "U, W, Out must be distinct");
+  if (n_terms < 0 || n_terms > 3 || (n_terms > 0 && (!Y || !ya))) return fail(c, TDG_ERR_INVALID_ARG, "bad terms");
+  VjpArgs a;
+  std::memset(&a, 0, sizeof(a));
+  for (int k = 0; k < n_terms; ++k) {
+    if (!Y[k] || Y[k] == Out) return fail(c, TDG_ERR_INVALID_ARG, "term array null or aliasing Out");
+    a.y[k] = Y[k];
+    a.ya[k] = ya[k];
+  }
+  a.n_terms = n_terms;
+  a.c = cw;
+  a.u = U;
+  a.w = W;
+  a.ubar = Out;
+  a.mesh = view(c);
+  a.tab = c->dev + c->off_vtab;
+  a.gamma = c->gamma;
+  for (int v = 0; v < 5; ++v) a.far[v] = c->far[v];
+  hipError_t e = launch_vjp(c->p, c->prec, a, (hipStream_t)s);
+  return e == hipSuccess ? TDG_OK : hip_fail(c, e, "vjp launch");
 }
 
 int tdg_residual_vjp(tdg_ctx* c, const void* U, const void* W, void* Ubar, void* s) {
@@ -568,6 +707,7 @@ int tdg_residual_vjp(tdg_ctx* c, const void* U, const void* W, void* Ubar, void*
   if (!U || !W || !Ubar || Ubar == U || Ubar == W) return fail(c, TDG_ERR_INVALID_ARG, "U, W, Ubar must be distinct");
   VjpArgs a;
   std::memset(&a, 0, sizeof(a));
+  a.c = 1.0;
   a.u = U;
   a.w = W;
   a.ubar = Ubar;
@@ -578,6 +718,14 @@ int tdg_residual_vjp(tdg_ctx* c, const void* U, const void* W, void* Ubar, void*
   hipError_t e = launch_vjp(c->p, c->prec, a, (hipStream_t)s);
   if (e == hipErrorNotSupported) return fail(c, TDG_ERR_UNSUPPORTED, "VJP not available for this mode");
   return e == hipSuccess ? TDG_OK : hip_fail(c, e, "vjp launch");
+}
+
+int tdg_wall_pressure(tdg_ctx* c, const void* U, double* J, void* dJdU, void* s) {
+  int st = require_bound(c);
+  if (st) return st;
+  if (!U || !J || (dJdU && dJdU == U)) return fail(c, TDG_ERR_INVALID_ARG, "bad pointers");
+  hipError_t e = launch_wall_pressure(c->p, c->prec, view(c), refview(c), c->gamma, U, J, dJdU, (hipStream_t)s);
+  return e == hipSuccess ? TDG_OK : hip_fail(c, e, "wall pressure launch");
 }
 
 int tdg_sync_check(tdg_ctx* c, void* s) {

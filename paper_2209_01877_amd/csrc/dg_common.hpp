@@ -49,25 +49,32 @@ struct Layout {
   }
 };
 
-// Adjoint (VJP) tables: transposed roles.  Rows are points, columns elements, and
-// the contraction runs over modes (weighted test functions) or over points.
-//   tinterp(qt, d, s): A[point][mode] = w_q dphi_m/dxi_d(xi_q)  (d = 0..2), and d = 3: phi_m(xi_q)
+// Adjoint (VJP) tables (f64 or f32, 16x16x4 operand layout).
+//   interp(qt, s)    : A[point][mode] = phi_m(xi_q)              (as the forward tables)
+//   trace(f, ft, s)  : A[point][mode] = phi_m(xi_f(q))
+//   tinterp(qt, d, s): A[point][mode] = w_q dphi_m/dxi_d(xi_q)
 //   ttrace(f, ft, s) : A[point][mode] = w^f_q phi_m(xi_f(q))
-//   tproj(mt, qt, j) : A[mode][point] = phi_m(xi_q)            (B^T: point values -> modes)
+//   tproj(mt, qt, j) : A[mode][point] = phi_m(xi_q)   (point values -> modes, accumulator order)
 //   tlift(mt,f,ft,j) : A[mode][point] = phi_m(xi_f(q))
 template <int P>
 struct VjpLayout {
   using O = Ord<P>;
   static constexpr int KS = (O::NP + 3) / 4;
+  static constexpr int n_interp = O::QT * KS;
+  static constexpr int n_trace = 4 * O::FT * KS;
   static constexpr int n_tinterp = O::QT * 3 * KS;
   static constexpr int n_ttrace = 4 * O::FT * KS;
   static constexpr int n_tproj = O::MT * O::QT * 4;
   static constexpr int n_tlift = O::MT * 4 * O::FT * 4;
-  static constexpr int off_tinterp = 0;
+  static constexpr int off_interp = 0;
+  static constexpr int off_trace = off_interp + n_interp;
+  static constexpr int off_tinterp = off_trace + n_trace;
   static constexpr int off_ttrace = off_tinterp + n_tinterp;
   static constexpr int off_tproj = off_ttrace + n_ttrace;
   static constexpr int off_tlift = off_tproj + n_tproj;
   static constexpr int n_slots = off_tlift + n_tlift;
+  __host__ __device__ static constexpr int interp(int qt, int s) { return off_interp + qt * KS + s; }
+  __host__ __device__ static constexpr int trace(int f, int ft, int s) { return off_trace + (f * O::FT + ft) * KS + s; }
   __host__ __device__ static constexpr int tinterp(int qt, int d, int s) { return off_tinterp + (qt * 3 + d) * KS + s; }
   __host__ __device__ static constexpr int ttrace(int f, int ft, int s) { return off_ttrace + (f * O::FT + ft) * KS + s; }
   __host__ __device__ static constexpr int tproj(int mt, int qt, int j) { return off_tproj + (mt * O::QT + qt) * 4 + j; }

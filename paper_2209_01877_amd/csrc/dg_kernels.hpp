@@ -67,13 +67,21 @@ __device__ __forceinline__ int drow_of(int g, int j) {
   return drow(Pr::f64, g, j);
 }
 
+// ---------------------------------------------------------------- arithmetic helpers
+// fp32 pointwise physics uses the hardware reciprocal and square root (about one ulp);
+// fp64 keeps correctly rounded division and square root.
+__device__ __forceinline__ float prec_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double prec_rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float prec_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double prec_sqrt(double x) { return sqrt(x); }
+
 // ---------------------------------------------------------------- Euler physics
 // Contravariant flux rows y_d = sum_e M[d][e] F_e(U) for d = 0..2, where F_e is the
 // Euler flux in direction e (eq. 2, 3-D) and M = |det J| J^-1.
 template <class T>
 __device__ __forceinline__ void contra_flux(const T u[5], const T M[9], T gm1, T y[3][5]) {
   const T rho = u[0];
-  const T ir = T(1) / rho;
+  const T ir = prec_rcp(rho);
   const T vx = u[1] * ir, vy = u[2] * ir, vz = u[3] * ir;
   const T p = gm1 * (u[4] - T(0.5) * (u[1] * vx + u[2] * vy + u[3] * vz));
   const T ep = u[4] + p;
@@ -93,12 +101,12 @@ __device__ __forceinline__ void contra_flux(const T u[5], const T M[9], T gm1, T
 template <class T>
 __device__ __forceinline__ void rusanov_n(const T um[5], const T up[5], const T N[3], T nn, T gamma, T out[5]) {
   const T gm1 = gamma - T(1);
-  const T irm = T(1) / um[0], irp = T(1) / up[0];
+  const T irm = prec_rcp(um[0]), irp = prec_rcp(up[0]);
   const T unm = (um[1] * N[0] + um[2] * N[1] + um[3] * N[2]) * irm;
   const T unp = (up[1] * N[0] + up[2] * N[1] + up[3] * N[2]) * irp;
   const T pm = gm1 * (um[4] - T(0.5) * (um[1] * um[1] + um[2] * um[2] + um[3] * um[3]) * irm);
   const T pp = gm1 * (up[4] - T(0.5) * (up[1] * up[1] + up[2] * up[2] + up[3] * up[3]) * irp);
-  const T cm = sqrt(gamma * pm * irm), cp = sqrt(gamma * pp * irp);
+  const T cm = prec_sqrt(gamma * pm * irm), cp = prec_sqrt(gamma * pp * irp);
   const T lm = fabs(unm) + cm * nn, lp = fabs(unp) + cp * nn;
   const T lam = lm > lp ? lm : lp;
   const T h = T(0.5);
@@ -115,7 +123,7 @@ template <class T>
 __device__ __forceinline__ void ghost_state(int tag, const T um[5], const T N[3], const T far[5], T up[5]) {
   if (tag == 2) {
     const T nn2 = N[0] * N[0] + N[1] * N[1] + N[2] * N[2];
-    const T mn = (um[1] * N[0] + um[2] * N[1] + um[3] * N[2]) / nn2;
+    const T mn = (um[1] * N[0] + um[2] * N[1] + um[3] * N[2]) * prec_rcp(nn2);
     up[0] = um[0];
     up[1] = um[1] - T(2) * mn * N[0];
     up[2] = um[2] - T(2) * mn * N[1];
@@ -133,7 +141,7 @@ template <class T>
 __device__ __forceinline__ void face_normal(int f, const double M[9], T N[3]) {
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
-    const double v = f == 0 ? (M[e] + M[3 + e] + M[6 + e]) : -M[3 * (f - 1) + e];
+    const double v = f == 0 ? (M[e] + M[3 + e] + M[6 + e]) : f == 1 ? -M[e] : f == 2 ? -M[3 + e] : -M[6 + e];
     N[e] = T(v);
   }
 }

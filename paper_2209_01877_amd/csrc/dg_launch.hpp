@@ -15,15 +15,27 @@ struct StageArgs {
   int max_blocks;     // 0: fill the device once
   MeshView mesh;
   const void* tab;    // packed MFMA operand tables
-  const double* mom;  // mixed modes: [7][N_p] fp64 moments of the volume and face tables
+  const double* mom;       // mixed modes: [7][N_p] fp64 moments of the volume and face tables
+  const double* mean_tab;  // mixed modes: the moments as fp64 MFMA A operands, [MT][2][64]
   double gamma;
   double far[5];      // farfield conserved state
+  // mixed modes: low-precision operand companion of u_in (modes 1.. as bf16/fp16,
+  // [E][5][32 KS]) and its fp32 cell means ([5][E]); the stage result's companion is
+  // written to q_out / c0_out when they are non-null
+  const void* q_in;
+  const float* c0_in;
+  void* q_out;
+  float* c0_out;
 };
 
 struct VjpArgs {
   const void* u;      // state (internal layout, S)
   const void* w;      // cotangent (internal layout, S)
-  void* ubar;         // result (internal layout, S)
+  void* ubar;         // result (internal layout, S): c J^T W + sum_k a_k Y_k
+  double c;
+  int n_terms;
+  const void* y[3];
+  double ya[3];
   int max_blocks;
   MeshView mesh;
   const void* tab;    // packed VJP operand tables (f64 or f32)
@@ -35,13 +47,21 @@ struct RefView {
   const double* qx;   // [N_q][3]
   const double* qw;   // [N_q]
   const double* B;    // [N_q][N_p]
+  const double* fw;   // [N_f]
+  const double* Bf;   // [4][N_f][N_p]
 };
 
 hipError_t launch_stage(int p, int prec, const StageArgs& a, hipStream_t stream);
+// Build the operand companion (q, c0) of an fp64 state for the mixed modes.
+hipError_t launch_pack(int p, int prec, const MeshView& m, const void* u, void* q, float* c0, hipStream_t s);
+// Bytes of one operand companion (q and c0) for the mixed modes.
+size_t companion_bytes(int p, int64_t epad);
 hipError_t launch_vjp(int p, int prec, const VjpArgs& a, hipStream_t stream);
 hipError_t launch_set_state(int p, int prec, const MeshView& m, const double* user, void* internal, hipStream_t s);
 hipError_t launch_get_state(int p, int prec, const MeshView& m, const void* internal, double* user, hipStream_t s);
 hipError_t launch_volume_points(int p, const MeshView& m, const RefView& r, double* xyz, hipStream_t s);
+hipError_t launch_wall_pressure(int p, int prec, const MeshView& m, const RefView& r, double gamma, const void* u,
+                                double* J, void* grad, hipStream_t s);
 hipError_t launch_project(int p, int prec, const MeshView& m, const RefView& r, double gamma, const double* prim,
                           void* internal, hipStream_t s);
 

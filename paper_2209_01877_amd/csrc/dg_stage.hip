@@ -117,18 +117,23 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
   OperandMap<Pr, NP, KS> om;
   om.init(g, plane);
 
-  // contiguous range of 16-element groups per wavefront; consecutive logical blocks
-  // sit on the same XCD so neighbouring elements share an L2
+  // Work distribution: workgroups are dispatched round-robin over the 8 XCDs, so block b
+  // runs on XCD b % 8.  Each XCD owns one contiguous eighth of the 16-element groups and
+  // its wavefronts sweep that range together (group = start + k * waves + wave), so at any
+  // time an XCD's waves work on a narrow window of consecutive elements whose own and
+  // neighbour coefficients fit in that XCD's L2.
   const int nblk = gridDim.x;
-  const int lblk = (nblk % 8 == 0) ? (blockIdx.x % 8) * (nblk / 8) + blockIdx.x / 8 : blockIdx.x;
-  const int64_t nwave = (int64_t)nblk * (blockDim.x >> 6);
-  const int64_t wid = (int64_t)lblk * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int nwb = blockDim.x >> 6;
+  const int nx = (nblk % 8 == 0) ? 8 : 1;
+  const int xcd = blockIdx.x % nx;
+  const int64_t waves_x = (int64_t)(nblk / nx) * nwb;
+  const int64_t wave_x = (int64_t)(blockIdx.x / nx) * nwb + (threadIdx.x >> 6);
   const int64_t ngroups = epad / 16;
-  const int64_t per = (ngroups + nwave - 1) / nwave;
-  const int64_t g_begin = wid * per;
-  const int64_t g_end = g_begin + per < ngroups ? g_begin + per : ngroups;
+  const int64_t chunk = (ngroups + nx - 1) / nx;
+  const int64_t g_begin = xcd * chunk;
+  const int64_t g_end = g_begin + chunk < ngroups ? g_begin + chunk : ngroups;
 
-  for (int64_t grp = g_begin; grp < g_end; ++grp) {
+  for (int64_t grp = g_begin + wave_x; grp < g_end; grp += waves_x) {
     const int e = (int)(grp * 16 + col);
     const uint32_t eoff = (uint32_t)e * sizeof(S);
     double Md[9];
@@ -143,13 +148,18 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
     for (int f = 0; f < 4; ++f) nbr[f] = mv.nbr[f * epad + e];
 
     Op bc[5][KS];
-    load_operands<Pr, NP, KS>(ubase, var_bytes, eoff, om, bc);
-
     T c0t[5], ybar[3][5];
     if constexpr (Pr::mixed) {
+      const Op* q = reinterpret_cast<const Op*>(a.q_in);
 #pragma unroll
-      for (int v = 0; v < 5; ++v) c0t[v] = T(*reinterpret_cast<const S*>(ubase + (size_t)v * var_bytes + eoff));
+      for (int v = 0; v < 5; ++v) {
+#pragma unroll
+        for (int s = 0; s < KS; ++s) bc[v][s] = q[(((int64_t)e * 5 + v) * KS + s) * 4 + g];
+        c0t[v] = a.c0_in[v * epad + e];
+      }
       contra_flux<T>(c0t, Mt, gm1, ybar);
+    } else {
+      load_operands<Pr, NP, KS>(ubase, var_bytes, eoff, om, bc);
     }
 
     Acc acc[MT][5];
@@ -245,16 +255,19 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
       const int en = nbf >= 0 ? nbf : e;
       const uint32_t enoff = (uint32_t)en * sizeof(S);
       Op bn[5][KS];
-      load_operands<Pr, NP, KS>(ubase, var_bytes, enoff, om, bn);
       T c0n[5], fhbar[5];
       if constexpr (Pr::mixed) {
-        if (nbf >= 0) {
+        const Op* q = reinterpret_cast<const Op*>(a.q_in);
 #pragma unroll
-          for (int v = 0; v < 5; ++v) c0n[v] = T(*reinterpret_cast<const S*>(ubase + (size_t)v * var_bytes + enoff));
-        } else {
-          ghost_state<T>(-nbf, c0t, N, far, c0n);
+        for (int v = 0; v < 5; ++v) {
+#pragma unroll
+          for (int s = 0; s < KS; ++s) bn[v][s] = q[(((int64_t)en * 5 + v) * KS + s) * 4 + g];
+          c0n[v] = a.c0_in[v * epad + en];
         }
+        if (nbf < 0) ghost_state<T>(-nbf, c0t, N, far, c0n);
         rusanov_n<T>(c0t, c0n, N, nn, gamma, fhbar);
+      } else {
+        load_operands<Pr, NP, KS>(ubase, var_bytes, enoff, om, bn);
       }
 #pragma unroll 1
       for (int ft = 0; ft < FT; ++ft) {
@@ -331,25 +344,34 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
     }
 
     // ------------------------------------------------------------ epilogue
-    // mixed: fp64 projection of the cell-mean fluxes (volume moments and face moments)
-    double mean_r[MT][4][5];
+    // mixed: fp64 projection of the cell-mean fluxes, sum_k mom_k[i] Fbar_k with the three
+    // volume directions and the four faces (k = 0..6), as two fp64 MFMA k-steps per mode
+    // tile.  Lane group g supplies k = g (volume direction g, or face 0 for g = 3) and
+    // k = 4 + g (face g + 1, or zero); the table rows are permuted so that the fp64
+    // accumulator rows line up with the fp32 accumulator rows of the same lane.
+    d4_t mean_acc[Pr::mixed ? MT : 1][5];
     if constexpr (Pr::mixed) {
-      double c0[5], ybar64[3][5];
+      double c0[5], x0[5], x1[5], yg[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) c0[v] = double(*reinterpret_cast<const S*>(ubase + (size_t)v * var_bytes + eoff));
-      contra_flux<double>(c0, Md, a.gamma - 1.0, ybar64);
+      {
+        // contravariant mean flux in direction min(g, 2) only: blend the row of M arithmetically
+        // (a select chain would be turned into an indexed, stack-resident array)
+        const double w0 = g == 0 ? 1.0 : 0.0, w1 = g == 1 ? 1.0 : 0.0, w2 = g >= 2 ? 1.0 : 0.0;
+        double Mrow[9];
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int mode = 16 * mt + drow_of<Pr>(g, j);
-          const int mc = mode < NP ? mode : NP - 1;
-#pragma unroll
-          for (int v = 0; v < 5; ++v)
-            mean_r[mt][j][v] = a.mom[mc] * ybar64[0][v] + a.mom[NP + mc] * ybar64[1][v] + a.mom[2 * NP + mc] * ybar64[2][v];
+        for (int c = 0; c < 3; ++c) {
+          Mrow[c] = w0 * Md[c] + w1 * Md[3 + c] + w2 * Md[6 + c];
+          Mrow[3 + c] = 0.0;
+          Mrow[6 + c] = 0.0;
         }
-#pragma unroll 1
-      for (int f = 0; f < 4; ++f) {
+        double y3[3][5];
+        contra_flux<double>(c0, Mrow, a.gamma - 1.0, y3);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) yg[v] = y3[0][v];
+      }
+      {
+        const int f = g == 3 ? 0 : g + 1;
         double N[3], cn[5], fb[5];
         face_normal<double>(f, Md, N);
         const double nn = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
@@ -363,45 +385,131 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
         }
         rusanov_n<double>(c0, cn, N, nn, a.gamma, fb);
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
+        for (int v = 0; v < 5; ++v) {
+          x0[v] = g == 3 ? fb[v] : yg[v];
+          x1[v] = g == 3 ? 0.0 : fb[v];
+        }
+      }
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int mode = 16 * mt + drow_of<Pr>(g, j);
-            const int mc = mode < NP ? mode : NP - 1;
-            const double lm = a.mom[(3 + f) * NP + mc];
+      for (int mt = 0; mt < MT; ++mt) {
+        const double a0 = a.mean_tab[(2 * mt) * 64 + lane], a1 = a.mean_tab[(2 * mt + 1) * 64 + lane];
 #pragma unroll
-            for (int v = 0; v < 5; ++v) mean_r[mt][j][v] -= lm * fb[v];
-          }
+        for (int v = 0; v < 5; ++v) {
+          d4_t m = {0, 0, 0, 0};
+          m = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, x0[v], m, 0, 0, 0);
+          m = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, x1[v], m, 0, 0, 0);
+          mean_acc[mt][v] = m;
+        }
       }
     }
     const double ivol = mv.inv_vol[e];
     if (e < mv.n_elem) {
       const char* u0base = reinterpret_cast<const char*>(a.u0);
       char* obase = reinterpret_cast<char*>(a.u_out);
+      const bool comp = Pr::mixed && a.q_out != nullptr;
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
+      for (int mt = 0; mt < MT; ++mt) {
+        double o[5][4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int mode = 16 * mt + drow_of<Pr>(g, j);
-          if (mode < NP) {
 #pragma unroll
-            for (int v = 0; v < 5; ++v) {
-              double r = double(acc[mt][v][j]);
-              if constexpr (Pr::mixed) r += mean_r[mt][j][v];
-              r *= ivol;
+          for (int v = 0; v < 5; ++v) {
+            double r = double(acc[mt][v][j]);
+            if constexpr (Pr::mixed) r += mean_acc[mt][v][j];
+            r *= ivol;
+            o[v][j] = 0.0;
+            if (mode < NP) {
               const size_t off = (size_t)v * var_bytes + (size_t)mode * plane + eoff;
+              double out;
               if (a.rk) {
                 const double uin = double(*reinterpret_cast<const S*>(ubase + off));
                 const double u0 = a.alpha == 0.0 ? 0.0 : double(*reinterpret_cast<const S*>(u0base + off));
-                *reinterpret_cast<S*>(obase + off) = S(a.alpha * u0 + (1.0 - a.alpha) * (uin + a.dt * r));
+                out = a.alpha * u0 + (1.0 - a.alpha) * (uin + a.dt * r);
               } else {
-                *reinterpret_cast<S*>(obase + off) = S(r);
+                out = r;
               }
+              *reinterpret_cast<S*>(obase + off) = S(out);
+              o[v][j] = out;
             }
           }
         }
+        if constexpr (Pr::mixed) {
+          if (comp) {
+            // operand companion of the result: modes 1.. in the operand precision, mean in fp32
+            using E1 = typename Pr::E1;
+            typedef E1 e4_t __attribute__((ext_vector_type(4)));
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+              e4_t h;
+#pragma unroll
+              for (int j = 0; j < 4; ++j) {
+                const int mode = 16 * mt + 4 * g + j;
+                h[j] = (E1)((mode > 0 && mode < NP) ? float(o[v][j]) : 0.0f);
+              }
+              *reinterpret_cast<e4_t*>(reinterpret_cast<E1*>(a.q_out) + ((int64_t)e * 5 + v) * (32 * KS) + 16 * mt +
+                                       4 * g) = h;
+              if (mt == 0 && g == 0) a.c0_out[v * epad + e] = float(o[v][0]);
+            }
+          }
+        }
+      }
+      if constexpr (Pr::mixed) {
+        // zero the companion slots past the last mode tile
+        if (comp) {
+#pragma unroll
+          for (int mt = MT; mt < 2 * KS; ++mt)
+#pragma unroll
+            for (int v = 0; v < 5; ++v)
+              *reinterpret_cast<uint2*>(reinterpret_cast<typename Pr::E1*>(a.q_out) + ((int64_t)e * 5 + v) * (32 * KS) +
+                                        16 * mt + 4 * g) = uint2{0, 0};
+        }
+      }
     }
   }
+}
+
+// Operand companion of an fp64 state (mixed modes): one thread per (element, variable).
+template <int P, class Pr>
+__global__ void pack_kernel(MeshView m, const double* __restrict__ u, typename Pr::E1* __restrict__ q,
+                            float* __restrict__ c0) {
+  using O = Ord<P>;
+  constexpr int NP = O::NP, KS = Layout<P, 8>::KS;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= m.epad * 5) return;
+  const int64_t e = t / 5;
+  const int v = (int)(t % 5);
+  typename Pr::E1* dst = q + (e * 5 + v) * (32 * KS);
+#pragma unroll
+  for (int mode = 0; mode < 32 * KS; ++mode) {
+    const float x = (mode > 0 && mode < NP) ? float(u[(int64_t)(v * NP + mode) * m.epad + e]) : 0.0f;
+    dst[mode] = (typename Pr::E1)x;
+  }
+  c0[v * m.epad + e] = float(u[(int64_t)(v * NP) * m.epad + e]);
+}
+
+size_t companion_bytes(int p, int64_t epad) {
+  const int np = (p + 1) * (p + 2) * (p + 3) / 6;
+  const int ks = (np + 31) / 32;
+  const size_t q = (size_t)epad * 5 * 32 * ks * 2;
+  return ((q + 255) & ~(size_t)255) + (size_t)epad * 5 * sizeof(float);
+}
+
+hipError_t launch_pack(int p, int prec, const MeshView& m, const void* u, void* q, float* c0, hipStream_t s) {
+  const unsigned nb = (unsigned)((m.epad * 5 + 255) / 256);
+#define TDG_PACK(PP)                                                                                          \
+  if (p == PP) {                                                                                             \
+    if (prec == 2)                                                                                           \
+      hipLaunchKernelGGL((pack_kernel<PP, PrecBF16>), dim3(nb), dim3(256), 0, s, m, (const double*)u,        \
+                         (__bf16*)q, c0);                                                                    \
+    else                                                                                                     \
+      hipLaunchKernelGGL((pack_kernel<PP, PrecF16>), dim3(nb), dim3(256), 0, s, m, (const double*)u,         \
+                         (_Float16*)q, c0);                                                                  \
+    return hipGetLastError();                                                                                \
+  }
+  TDG_PACK(1) TDG_PACK(2) TDG_PACK(3) TDG_PACK(4)
+#undef TDG_PACK
+  return hipErrorInvalidValue;
 }
 
 template <int P, class Pr>

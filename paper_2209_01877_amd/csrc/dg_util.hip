@@ -58,6 +58,51 @@ __global__ void project_kernel(MeshView m, int np, int nq, RefView r, double gam
   for (int c = 0; c < 5; ++c) out[(int64_t)(c * np + i) * m.epad + n] = S(acc[c]);
 }
 
+// Integrated slip-wall pressure J = sum_{wall faces} sum_q 2 A_f w^f_q p(U-_q) and dJ/dU,
+// one thread per element (fp64).  J accumulates atomically into *J (zeroed by the caller).
+template <class S>
+__global__ void wall_pressure_kernel(MeshView m, int np, int nf, RefView r, double gamma, const S* __restrict__ u,
+                                     double* __restrict__ J, S* __restrict__ grad) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= m.epad) return;
+  const double gm1 = gamma - 1.0;
+  double Jloc = 0.0;
+  const bool real = e < m.n_elem;
+  if (grad)
+    for (int v = 0; v < 5; ++v)
+      for (int i = 0; i < np; ++i) grad[(int64_t)(v * np + i) * m.epad + e] = S(0);
+  for (int f = 0; f < 4 && real; ++f) {
+    if (m.nbr[f * m.epad + e] != -2) continue;
+    double Mr[9];
+    for (int k = 0; k < 9; ++k) Mr[k] = m.M[k * m.epad + e];
+    double N[3];
+    for (int c = 0; c < 3; ++c)
+      N[c] = f == 0 ? (Mr[c] + Mr[3 + c] + Mr[6 + c]) : f == 1 ? -Mr[c] : f == 2 ? -Mr[3 + c] : -Mr[6 + c];
+    const double area2 = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);  // 2 A_f
+    for (int q = 0; q < nf; ++q) {
+      const double* bq = r.Bf + ((int64_t)f * nf + q) * np;
+      double U[5] = {0, 0, 0, 0, 0};
+      for (int v = 0; v < 5; ++v)
+        for (int i = 0; i < np; ++i) U[v] += bq[i] * double(u[(int64_t)(v * np + i) * m.epad + e]);
+      const double ir = 1.0 / U[0];
+      const double vel[3] = {U[1] * ir, U[2] * ir, U[3] * ir};
+      const double q2 = vel[0] * vel[0] + vel[1] * vel[1] + vel[2] * vel[2];
+      const double p = gm1 * (U[4] - 0.5 * U[0] * q2);
+      const double wq = area2 * r.fw[q];
+      Jloc += wq * p;
+      if (grad) {
+        const double dp[5] = {gm1 * 0.5 * q2, -gm1 * vel[0], -gm1 * vel[1], -gm1 * vel[2], gm1};
+        for (int v = 0; v < 5; ++v)
+          for (int i = 0; i < np; ++i) {
+            S* gp = grad + (int64_t)(v * np + i) * m.epad + e;
+            *gp = S(double(*gp) + wq * dp[v] * bq[i]);
+          }
+      }
+    }
+  }
+  if (Jloc != 0.0) atomicAdd(J, Jloc);
+}
+
 inline int np_of(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
@@ -86,6 +131,20 @@ hipError_t launch_get_state(int p, int prec, const MeshView& m, const void* inte
 hipError_t launch_volume_points(int p, const MeshView& m, const RefView& r, double* xyz, hipStream_t s) {
   const int nq = (p + 1) * (p + 1) * (p + 1);
   hipLaunchKernelGGL(volume_points_kernel, dim3(nblocks(m.n_elem * nq, 256)), dim3(256), 0, s, m, nq, r, xyz);
+  return hipGetLastError();
+}
+
+hipError_t launch_wall_pressure(int p, int prec, const MeshView& m, const RefView& r, double gamma, const void* u,
+                                double* J, void* grad, hipStream_t s) {
+  const int np = np_of(p), nf = (p + 1) * (p + 1);
+  hipError_t e = hipMemsetAsync(J, 0, sizeof(double), s);
+  if (e != hipSuccess) return e;
+  if (prec == 1)
+    hipLaunchKernelGGL(wall_pressure_kernel<float>, dim3(nblocks(m.epad, 128)), dim3(128), 0, s, m, np, nf, r, gamma,
+                       (const float*)u, J, (float*)grad);
+  else
+    hipLaunchKernelGGL(wall_pressure_kernel<double>, dim3(nblocks(m.epad, 128)), dim3(128), 0, s, m, np, nf, r,
+                       gamma, (const double*)u, J, (double*)grad);
   return hipGetLastError();
 }
 

@@ -145,14 +145,18 @@ class Solver:
         return out
 
     def new_work(self) -> torch.Tensor:
-        return torch.empty((2, 5, self.n_modes, self.n_elem_pad), dtype=self.state_dtype, device=self.device)
+        size = ctypes.c_size_t()
+        check(lib.tdg_work_bytes(self._ctx, ctypes.byref(size)), self._ctx)
+        return torch.empty(size.value, dtype=torch.uint8, device=self.device)
 
     def rk_step(self, U: torch.Tensor, dt: float, n_steps: int = 1, work: torch.Tensor | None = None,
                 stream=None) -> torch.Tensor:
         """n SSP-RK3 steps in place on U (internal layout)."""
         self._check_state(U)
         work = self.new_work() if work is None else work
-        assert work.dtype == self.state_dtype and work.numel() >= 2 * U.numel()
+        size = ctypes.c_size_t()
+        check(lib.tdg_work_bytes(self._ctx, ctypes.byref(size)), self._ctx)
+        assert work.is_cuda and work.numel() * work.element_size() >= size.value
         check(lib.tdg_rk_step(self._ctx, _ptr(U), _ptr(work), float(dt), int(n_steps), _stream(stream)),
               self._ctx, "tdg_rk_step")
         return U
@@ -165,6 +169,38 @@ class Solver:
         check(lib.tdg_residual_vjp(self._ctx, _ptr(U), _ptr(W), _ptr(out), _stream(stream)), self._ctx,
               "tdg_residual_vjp")
         return out
+
+    def rk_stage(self, U_in: torch.Tensor, U0: torch.Tensor | None, out: torch.Tensor, alpha: float, dt: float,
+                 stream=None) -> torch.Tensor:
+        """One SSP-RK3 stage: out = alpha U0 + (1 - alpha)(U_in + dt R(U_in))."""
+        self._check_state(U_in)
+        self._check_state(out)
+        u0 = None if U0 is None else ctypes.c_void_p(_ptr(U0))
+        check(lib.tdg_rk_stage(self._ctx, _ptr(U_in), u0, _ptr(out), float(alpha), float(dt), _stream(stream)),
+              self._ctx, "tdg_rk_stage")
+        return out
+
+    def residual_vjp_axpy(self, U: torch.Tensor, W: torch.Tensor, c: float, terms, out: torch.Tensor,
+                          stream=None) -> torch.Tensor:
+        """out = c (dR/dU)^T W + sum a_k Y_k for terms = [(a_k, Y_k), ...] (at most three)."""
+        self._check_state(U)
+        self._check_state(W)
+        self._check_state(out)
+        n = len(terms)
+        ptrs = (ctypes.c_void_p * 3)(*([_ptr(y) for _, y in terms] + [None] * (3 - n)))
+        coef = (ctypes.c_double * 3)(*([float(a) for a, _ in terms] + [0.0] * (3 - n)))
+        check(lib.tdg_residual_vjp_axpy(self._ctx, _ptr(U), _ptr(W), float(c), n, ptrs, coef, _ptr(out),
+                                        _stream(stream)), self._ctx, "tdg_residual_vjp_axpy")
+        return out
+
+    def wall_pressure(self, U: torch.Tensor, grad: bool = False, stream=None):
+        """Integrated slip-wall pressure J(U) (0-d device tensor) and, if asked, dJ/dU (internal)."""
+        self._check_state(U)
+        J = torch.empty((), dtype=torch.float64, device=self.device)
+        g = self.new_state() if grad else None
+        check(lib.tdg_wall_pressure(self._ctx, _ptr(U), _ptr(J), None if g is None else ctypes.c_void_p(_ptr(g)),
+                                    _stream(stream)), self._ctx, "tdg_wall_pressure")
+        return (J, g) if grad else J
 
     def sync(self, stream=None) -> None:
         check(lib.tdg_sync_check(self._ctx, _stream(stream)), self._ctx, "tdg_sync_check")

@@ -1,0 +1,126 @@
+"""GPU adjoint: the VJP kernel against the oracle's reverse-mode adjoint, against central
+finite differences of the GPU residual at the differentiation-form size, and the
+checkpointed SSP-RK3 trajectory adjoint against the oracle's trajectory adjoint."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.adjoint import residual_vjp as oracle_vjp
+from oracle.adjoint import trajectory_vjp as oracle_traj
+from synthetic import fields, kuhn_cube
+
+pytestmark = pytest.mark.gpu
+
+from gpu_common import make_mesh, oracle, random_state, rel_err, solver  # noqa: E402
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5, "bf16": 1e-12, "fp16": 1e-12}
+
+
+def gpu_vjp(s, U, W):
+    Ui = s.set_state(U.cuda().contiguous())
+    Wi = s.set_state(W.cuda().contiguous())
+    out = s.get_state(s.residual_vjp(Ui, Wi)).cpu()
+    s.sync()
+    return out
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_vjp_vs_oracle(p, prec):
+    mesh = make_mesh("ragged")
+    dg = oracle(p, mesh)
+    U = random_state(dg, seed=5)
+    W = torch.from_numpy(fields.gaussian(U.shape, 43))
+    ref = oracle_vjp(dg, U, W)
+    got = gpu_vjp(solver(p, prec, mesh), U, W)
+    err = rel_err(dg, got, ref)
+    print(f"p={p} {prec} vjp rel L2 error {err:.3e}")
+    assert err < TOL[prec]
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_vjp_boundaries(p):
+    far = (1.0, 0.5 * math.sqrt(1.4), 0.0, 0.0, 1.0)
+    mesh = make_mesh("bump")
+    dg = oracle(p, mesh, far)
+    U = random_state(dg, seed=8)
+    W = torch.from_numpy(fields.gaussian(U.shape, 43))
+    ref = oracle_vjp(dg, U, W)
+    got = gpu_vjp(solver(p, "fp64", mesh, farfield=far), U, W)
+    err = rel_err(dg, got, ref)
+    print(f"p={p} boundary vjp rel L2 error {err:.3e}")
+    assert err < 1e-12
+
+
+def test_vjp_c4_subset_vs_oracle():
+    """P2 on the jittered 4^3 x 6 cube with the differentiation-form seeds (state 42, W 43)."""
+    mesh = kuhn_cube(4, jitter=0.2, jitter_seed=1877, shuffle_seed=2209)
+    dg = oracle(2, mesh)
+    U = dg.project(fields.RandomSmooth(42))
+    W = torch.from_numpy(fields.gaussian(U.shape, 43))
+    ref = oracle_vjp(dg, U, W)
+    got = gpu_vjp(solver(2, "fp64", mesh), U, W)
+    assert rel_err(dg, got, ref) < 1e-12
+
+
+def test_vjp_c4_finite_difference():
+    """P2 on the jittered 40^3 x 6 cube (384,000 tets): <W, (R(U+eV) - R(U-eV))/2e> against
+    <VJP(W), V> with eps = 1e-6, FP64, state RandomSmooth(42), W and V Gaussian (seeds 43, 44)."""
+    mesh = kuhn_cube(40, jitter=0.2, jitter_seed=1877, shuffle_seed=2209)
+    s = solver(2, "fp64", mesh)
+    U = s.project_fn(fields.RandomSmooth(42))
+    g = torch.Generator(device="cuda").manual_seed(43)
+    W = torch.randn(U.shape, dtype=torch.float64, device="cuda", generator=g)
+    g.manual_seed(44)
+    V = torch.randn(U.shape, dtype=torch.float64, device="cuda", generator=g)
+    W[:, :, mesh.n_elem:] = 0
+    V[:, :, mesh.n_elem:] = 0
+    eps = 1e-6
+    Rp = s.residual(U + eps * V)
+    Rm = s.residual(U - eps * V)
+    lhs = (W * (Rp - Rm)).sum().item() / (2 * eps)
+    rhs = (s.residual_vjp(U, W) * V).sum().item()
+    s.sync()
+    print(f"C4 FD dot product: {lhs:.12e} vs {rhs:.12e}, rel {abs(lhs - rhs) / abs(rhs):.2e}")
+    assert abs(lhs - rhs) < 1e-6 * abs(rhs)
+
+
+def test_autograd_residual():
+    from paper_2209_01877_amd.autograd import residual
+
+    mesh = make_mesh("jitter4")
+    dg = oracle(2, mesh)
+    U = random_state(dg, seed=3)
+    W = torch.from_numpy(fields.gaussian(U.shape, 7))
+    s = solver(2, "fp64", mesh)
+    Ui = s.set_state(U.cuda()).requires_grad_(True)
+    Wi = s.set_state(W.cuda())
+    R = residual(s, Ui)
+    (g,) = torch.autograd.grad(R, Ui, Wi)
+    got = s.get_state(g.contiguous()).cpu()
+    assert rel_err(dg, got, oracle_vjp(dg, U, W)) < 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16"])
+def test_trajectory_adjoint(prec):
+    """d<W, U_n>/dU_0 through 5 SSP-RK3 steps with checkpoints every 2 steps.  In fp64 it
+    must match the oracle's trajectory adjoint; the mixed forward's adjoint is taken in fp64
+    around the mixed stage states and is compared with a looser bound."""
+    from paper_2209_01877_amd.autograd import rk_trajectory
+
+    mesh = make_mesh("jitter4")
+    dg = oracle(1, mesh)
+    U0 = random_state(dg, seed=5, scale=0.005)
+    dt = 0.5 * dg.stable_dt(U0)
+    W = torch.from_numpy(fields.gaussian(U0.shape, 43))
+    ref = oracle_traj(dg, U0, dt, 5, W, checkpoint_every=2)
+    s = solver(1, prec, mesh)
+    Ui = s.set_state(U0.cuda()).requires_grad_(True)
+    Un = rk_trajectory(s, Ui, dt, 5, checkpoint_every=2)
+    (g,) = torch.autograd.grad(Un, Ui, s.set_state(W.cuda()))
+    got = s.get_state(g.contiguous()).cpu()
+    err = rel_err(dg, got, ref)
+    print(f"{prec} trajectory adjoint rel L2 error {err:.3e}")
+    assert err < (1e-12 if prec == "fp64" else 1e-3)

@@ -180,3 +180,19 @@ def test_boundary_faces():
     lam = abs(un) + math.sqrt(1.4 * p / rho)
     assert abs(F[0]) < 1e-14 and abs(F[4]) < 1e-14
     assert torch.allclose(F[1:4], (p + rho * un * (un + lam)) * n[0], atol=1e-14, rtol=0)
+
+
+def test_wall_pressure_uniform_state():
+    """For a uniform state the integrated wall pressure is p times the wall area (sum of the
+    wall triangles' areas from their corner coordinates)."""
+    m = kuhn_cube(4, periodic=(False, False, True), jitter=0.2, bump_height=0.05)
+    dg = DG(2, m.elem_vid, m.elem_xyz, m.bface_vid, m.bface_tag)
+    U = dg.project(lambda x: fields.freestream(x, 1.2, (0.3, 0.0, 0.1), 0.8))
+    # wall triangles: boundary faces tagged 2, coordinates from the elements that own them
+    area = 0.0
+    for k in torch.nonzero(dg.f_tag == 2).flatten().tolist():
+        e, f = int(dg.f_em[k]), int(dg.f_fm[k])
+        X = dg.geo.xyz[e]
+        a, b, c = [X[v] for v in range(4) if v != f]
+        area += 0.5 * np.linalg.norm(np.cross(b - a, c - a))
+    assert abs(dg.wall_pressure(U).item() - 0.8 * area) < 1e-13 * area
