@@ -18,7 +18,7 @@
  *   quadrature  collapsed Gauss-Jacobi, n = p+1 points per direction (tet n^3,
  *               triangle n^2), exact to degree 2p+1.
  *   face flux   Rusanov (local Lax-Friedrichs), lambda = max(|u.n|+c) over both
- *               sides per quadrature point.  The paper uses Roe.
+ *               sides per quadrature point; Roe (the paper's flux) as an option.
  *   boundaries  ghost states: farfield = free stream, slip wall = mirrored normal
  *               momentum (eq. 11 boundary-face term).
  *   time        SSP-RK3 in Shu-Osher form (the paper uses explicit 2nd-order RK).
@@ -75,6 +75,11 @@ typedef enum {
 
 typedef enum { TDG_BC_FARFIELD = 1, TDG_BC_SLIPWALL = 2 } tdg_bc;
 
+typedef enum {
+  TDG_FLUX_RUSANOV = 0, /* local Lax-Friedrichs (default) */
+  TDG_FLUX_ROE = 1      /* Roe's flux (the paper's, Sec. II.B), Harten entropy fix 0.1 c */
+} tdg_flux;
+
 /* ------------------------------------------------------------------ context */
 
 /* Create a context for polynomial order p (1..4) and a precision mode.  gamma is the
@@ -96,7 +101,10 @@ int tdg_sizes(const tdg_ctx* ctx, int* n_modes, int* n_vol_points, int* n_face_p
 /* Upload a tetrahedral mesh (host arrays, copied).  Builds the face adjacency by
  * matching sorted vertex-id triples, tags boundary faces, computes FP64 geometry and
  * renumbers the elements (the grid renumbering of Sec. III.B: RCM, or a space-filling
- * curve).  The renumbering runs once, before time stepping.
+ * curve).  The renumbering runs once, before time stepping.  For the FP64 and FP32 modes
+ * the RCM and curve orders are then refined inside windows of 256 elements by grouping
+ * elements with equal neighbour face codes (fewer distinct face tables per 16-element
+ * tile in the stage kernel); the mixed modes keep the plain order.
  *   elem_vid   host int64 [n_elem][4]   global vertex ids (on a torus: periodic ids)
  *   elem_xyz   host double [n_elem][4][3] vertex coordinates, per element, unwrapped
  *   bface_vid  host int64 [n_bface][3]  boundary faces (any vertex order), may be NULL if 0
@@ -117,13 +125,18 @@ int tdg_mesh_device_bytes(const tdg_ctx* ctx, size_t* bytes);
  * context computes.  Errors: TDG_ERR_STATE (no mesh), TDG_ERR_INVALID_ARG, TDG_ERR_HIP. */
 int tdg_mesh_bind(tdg_ctx* ctx, void* dev_buf, size_t bytes, void* hip_stream);
 
+/* Interface flux of eq. 11 (a tdg_flux value; default Rusanov).  The adjoint entry points
+ * return TDG_ERR_UNSUPPORTED with the Roe flux. */
+int tdg_set_flux(tdg_ctx* ctx, int flux);
+
 /* Free-stream primitive state (rho, u, v, w, p) used as the farfield ghost (host array). */
 int tdg_set_farfield(tdg_ctx* ctx, const double prim[5]);
 
-/* Mesh statistics after renumbering (host int64 out[6]): n_elem, n_elem_pad,
+/* Mesh statistics after renumbering (host int64 out[7]): n_elem, n_elem_pad,
  * interior faces, boundary faces, max |i - j| over face neighbours (bandwidth),
- * and the number of neighbour pairs with |i - j| < 64. */
-int tdg_mesh_stats(const tdg_ctx* ctx, int64_t out[6]);
+ * the number of neighbour pairs with |i - j| < 64, and the number of distinct neighbour
+ * face tables summed over (16-element tile, face) pairs (MFMA chains of the stage kernel). */
+int tdg_mesh_stats(const tdg_ctx* ctx, int64_t out[7]);
 
 /* ------------------------------------------------------------------ state */
 
@@ -192,6 +205,12 @@ int tdg_residual_vjp_axpy(tdg_ctx* ctx, const void* U, const void* W, double c, 
  * NULL to skip).  J: device double, overwritten.  The objective of the full configuration's
  * adjoint (its gradient seeds the trajectory adjoint). */
 int tdg_wall_pressure(tdg_ctx* ctx, const void* U, double* J, void* dJdU, void* hip_stream);
+
+/* Explicit time step as the global minimum of local steps (the paper's minimum over the
+ * local time steps of all cells, Sec. III.C, computed by a GPU reduction):
+ *   dt = min_K cfl d_K / ((2p+1)(|u_K| + c_K)),  d_K = 6|K| / sum_f A_f,
+ * with u_K, c_K from the cell means of U.  dt: device double, overwritten. */
+int tdg_stable_dt(tdg_ctx* ctx, const void* U, double cfl, double* dt, void* hip_stream);
 
 /* Synchronise the stream; map a pending asynchronous HIP error to TDG_ERR_HIP. */
 int tdg_sync_check(tdg_ctx* ctx, void* hip_stream);

@@ -33,10 +33,11 @@ GAMMA = 1.4
 class DG:
     def __init__(self, p: int, elem_vid, elem_xyz, bface_vid=None, bface_tag=None,
                  gamma: float = GAMMA, farfield_prim=(1.0, 0.5 * np.sqrt(1.4), 0.0, 0.0, 1.0),
-                 chunk: int = 65536):
+                 chunk: int = 65536, flux: str = "rusanov"):
         self.p = p
         self.gamma = gamma
         self.chunk = chunk
+        self.flux = flux
         self.geo = build_geometry(elem_vid, elem_xyz)
         self.faces = build_faces(self.geo.vid, bface_vid, bface_tag)
         n = p + 1
@@ -124,7 +125,10 @@ class DG:
                 wall = euler.slipwall_ghost(Um, n.expand(Um.shape[:-1] + (3,)))
                 ghost = torch.where((tag == 2)[:, None, None], wall, far)
                 Up = torch.where(interior[:, None, None], Up, ghost)
-            Fhat = euler.rusanov(Um, Up, n, self.gamma)                          # (F, Nf, 5)
+            if self.flux == "roe":
+                Fhat = euler.roe(Um, Up, n, self.gamma)
+            else:
+                Fhat = euler.rusanov(Um, Up, n, self.gamma)                      # (F, Nf, 5)
             scale = 2.0 * self.f_area[fi][:, None, None]
             Sm = scale * torch.einsum("q,fqi,fqv->fvi", self.wf, Bm, Fhat)
             Sp = scale * torch.einsum("q,fqi,fqv->fvi", self.wf, Bp, Fhat)
@@ -166,6 +170,16 @@ class DG:
         speed = torch.linalg.norm(mean[:, 1:4], dim=1) / rho
         c = torch.sqrt(self.gamma * euler.pressure(mean, self.gamma) / rho)
         return float(cfl * d.min() / ((2 * self.p + 1) * (speed + c).max()))
+
+    def local_dt_min(self, U: torch.Tensor, cfl: float = 0.2) -> float:
+        """min_K cfl d_K / ((2p+1)(|u_K| + c_K)): the minimum of the local explicit steps over
+        all cells (the paper's time-step reduction), cell means of U."""
+        d = torch.from_numpy(6.0 * self.geo.volume / self.geo.area.sum(1))
+        mean = U[:, :, 0]
+        rho = mean[:, 0]
+        speed = torch.linalg.norm(mean[:, 1:4], dim=1) / rho
+        c = torch.sqrt(self.gamma * euler.pressure(mean, self.gamma) / rho)
+        return float((cfl * d / ((2 * self.p + 1) * (speed + c))).min())
 
     # ---------------------------------------------------------------- norms
     def l2_norm(self, U: torch.Tensor) -> torch.Tensor:

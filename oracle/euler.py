@@ -67,6 +67,49 @@ def rusanov(Um: torch.Tensor, Up: torch.Tensor, n: torch.Tensor, gamma: float) -
     return 0.5 * (normal_flux(Um, n, gamma) + normal_flux(Up, n, gamma)) - 0.5 * lam[..., None] * (Up - Um)
 
 
+def roe(Um: torch.Tensor, Up: torch.Tensor, n: torch.Tensor, gamma: float, delta: float = 0.1) -> torch.Tensor:
+    """Roe's approximate Riemann flux (the paper's inviscid interface flux, Sec. II.B).
+
+    Fhat = (F(U-).n + F(U+).n)/2 - 1/2 sum_k |lambda_k| alpha_k r_k with Roe averages
+    (square-root-density weights) of velocity and total enthalpy, acoustic waves
+    u.n -+ c, and the entropy and shear waves at u.n.  Harten's entropy fix on the
+    acoustic waves: |lambda| -> (lambda^2 + d^2)/(2 d) when |lambda| < d, d = delta c."""
+    rl, rr = Um[..., 0], Up[..., 0]
+    ul, ur = Um[..., 1:4] / rl[..., None], Up[..., 1:4] / rr[..., None]
+    pl, pr = pressure(Um, gamma), pressure(Up, gamma)
+    hl, hr = (Um[..., 4] + pl) / rl, (Up[..., 4] + pr) / rr
+    sl, sr = torch.sqrt(rl), torch.sqrt(rr)
+    w = sl + sr
+    rho = sl * sr
+    u = (sl[..., None] * ul + sr[..., None] * ur) / w[..., None]
+    h = (sl * hl + sr * hr) / w
+    q2 = (u * u).sum(-1)
+    c = torch.sqrt((gamma - 1.0) * (h - 0.5 * q2))
+    un = (u * n).sum(-1)
+    dr = rr - rl
+    dp = pr - pl
+    du = ur - ul
+    dun = (du * n).sum(-1)
+
+    def fix(lam):
+        d = delta * c
+        a = lam.abs()
+        return torch.where(a < d, (lam * lam + d * d) / (2.0 * d), a)
+
+    l1, l2, l4 = fix(un - c), un.abs(), fix(un + c)
+    a1 = (dp - rho * c * dun) / (2.0 * c * c)
+    a2 = dr - dp / (c * c)
+    a4 = (dp + rho * c * dun) / (2.0 * c * c)
+    ones = torch.ones_like(rl)
+    r1 = torch.cat([ones[..., None], u - c[..., None] * n, (h - un * c)[..., None]], -1)
+    r2 = torch.cat([ones[..., None], u, (0.5 * q2)[..., None]], -1)
+    r4 = torch.cat([ones[..., None], u + c[..., None] * n, (h + un * c)[..., None]], -1)
+    shear_m = du - dun[..., None] * n
+    r3 = torch.cat([torch.zeros_like(rl)[..., None], shear_m, ((u * du).sum(-1) - un * dun)[..., None]], -1)
+    diss = (l1 * a1)[..., None] * r1 + (l2 * a2)[..., None] * r2 + (l2 * rho)[..., None] * r3 + (l4 * a4)[..., None] * r4
+    return 0.5 * (normal_flux(Um, n, gamma) + normal_flux(Up, n, gamma)) - 0.5 * diss
+
+
 def slipwall_ghost(Um: torch.Tensor, n: torch.Tensor) -> torch.Tensor:
     mn = (Um[..., 1:4] * n).sum(-1, keepdim=True)
     return torch.cat([Um[..., :1], Um[..., 1:4] - 2.0 * mn * n, Um[..., 4:]], dim=-1)

@@ -33,6 +33,7 @@ _SIGS = {
     "tdg_mesh_device_bytes": (_i, [_p, ctypes.POINTER(_sz)]),
     "tdg_mesh_bind": (_i, [_p, _p, _sz, _p]),
     "tdg_set_farfield": (_i, [_p, _p]),
+    "tdg_set_flux": (_i, [_p, _i]),
     "tdg_mesh_stats": (_i, [_p, _p]),
     "tdg_state_elems": (_i, [_p, ctypes.POINTER(_i64)]),
     "tdg_state_bytes": (_i, [_p, ctypes.POINTER(_sz)]),
@@ -47,6 +48,7 @@ _SIGS = {
     "tdg_rk_stage": (_i, [_p, _p, _p, _p, _d, _d, _p]),
     "tdg_residual_vjp_axpy": (_i, [_p, _p, _p, _d, _i, _p, _p, _p, _p]),
     "tdg_wall_pressure": (_i, [_p, _p, _p, _p, _p]),
+    "tdg_stable_dt": (_i, [_p, _p, _d, _p, _p]),
     "tdg_sync_check": (_i, [_p, _p]),
     "tdg_debug_tables": (_i, [_i, _i, _p, _sz, ctypes.POINTER(_sz)]),
 }

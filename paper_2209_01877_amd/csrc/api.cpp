@@ -24,7 +24,7 @@ struct tdg_ctx {
   RefElem ref;
   std::string err;
   bool has_mesh = false, bound = false;
-  int64_t n = 0, epad = 0, n_interior = 0, n_boundary = 0, bandwidth = 0, near64 = 0;
+  int64_t n = 0, epad = 0, n_interior = 0, n_boundary = 0, bandwidth = 0, near64 = 0, tile_tables = 0;
   // host images of the device arrays (internal element order)
   std::vector<double> M, inv_vol, x0j;
   std::vector<int32_t> nbr, fcode, perm;
@@ -36,6 +36,7 @@ struct tdg_ctx {
   size_t off_M = 0, off_iv = 0, off_x0j = 0, off_nbr = 0, off_fcode = 0, off_perm = 0, off_stab = 0, off_vtab = 0,
          off_mom = 0, off_mtab = 0, off_qx = 0, off_qw = 0, off_B = 0, off_fw = 0, off_Bf = 0, off_comp = 0, total = 0;
   double far[5] = {1.0, 0.0, 0.0, 0.0, 2.5};
+  int flux = TDG_FLUX_RUSANOV;
 };
 
 namespace {
@@ -369,7 +370,9 @@ int tdg_mesh_upload(tdg_ctx* c, int64_t n_elem, const int64_t* elem_vid, const d
     std::vector<double> M, iv, x0j;
     msg = build_geometry(hm, M, iv, x0j);
     if (!msg.empty()) return fail(c, TDG_ERR_MESH, msg);
-    const std::vector<int64_t> order = renumber(hm, renumber_mode);  // new -> old
+    // the compute-bound fp64/fp32 kernels gain from fewer neighbour face tables per tile; the
+    // memory-bound mixed kernels keep the tighter spatial order
+    const std::vector<int64_t> order = renumber(hm, renumber_mode, !is_mixed(c));  // new -> old
     std::vector<int64_t> inv(n_elem);
     for (int64_t i = 0; i < n_elem; ++i) inv[order[i]] = i;
     const int64_t epad = (n_elem + 63) / 64 * 64;
@@ -411,6 +414,16 @@ int tdg_mesh_upload(tdg_ctx* c, int64_t n_elem, const int64_t* elem_vid, const d
     }
     c->bandwidth = bw;
     c->near64 = near;
+    // distinct neighbour face tables per (16-element tile, face), summed over tiles and faces
+    int64_t tt = 0;
+    for (int64_t t0 = 0; t0 < epad; t0 += 16)
+      for (int f = 0; f < 4; ++f) {
+        int mask = 0;
+        for (int64_t i = t0; i < t0 + 16 && i < n_elem; ++i)
+          if (c->nbr[f * epad + i] >= 0) mask |= 1 << ((c->fcode[i] >> (2 * f)) & 3);
+        tt += __builtin_popcount(mask);
+      }
+    c->tile_tables = tt;
     if (perm_new_to_old)
       for (int64_t i = 0; i < n_elem; ++i) perm_new_to_old[i] = order[i];
     // device layout
@@ -495,6 +508,13 @@ int tdg_mesh_bind(tdg_ctx* c, void* dev_buf, size_t bytes, void* hip_stream) {
   return TDG_OK;
 }
 
+int tdg_set_flux(tdg_ctx* c, int flux) {
+  if (!c) return TDG_ERR_INVALID_ARG;
+  if (flux != TDG_FLUX_RUSANOV && flux != TDG_FLUX_ROE) return fail(c, TDG_ERR_INVALID_ARG, "unknown flux");
+  c->flux = flux;
+  return TDG_OK;
+}
+
 int tdg_set_farfield(tdg_ctx* c, const double prim[5]) {
   if (!c || !prim) return TDG_ERR_INVALID_ARG;
   if (!(prim[0] > 0.0) || !(prim[4] > 0.0)) return fail(c, TDG_ERR_INVALID_ARG, "farfield density and pressure must be positive");
@@ -507,7 +527,7 @@ int tdg_set_farfield(tdg_ctx* c, const double prim[5]) {
   return TDG_OK;
 }
 
-int tdg_mesh_stats(const tdg_ctx* c, int64_t out[6]) {
+int tdg_mesh_stats(const tdg_ctx* c, int64_t out[7]) {
   if (!c || !out) return TDG_ERR_INVALID_ARG;
   if (!c->has_mesh) return TDG_ERR_STATE;
   out[0] = c->n;
@@ -516,6 +536,7 @@ int tdg_mesh_stats(const tdg_ctx* c, int64_t out[6]) {
   out[3] = c->n_boundary;
   out[4] = c->bandwidth;
   out[5] = c->near64;
+  out[6] = c->tile_tables;
   return TDG_OK;
 }
 
@@ -574,6 +595,7 @@ static StageArgs stage_args(const tdg_ctx* c) {
   a.mean_tab = (const double*)(c->dev + c->off_mtab);
   a.gamma = c->gamma;
   for (int v = 0; v < 5; ++v) a.far[v] = c->far[v];
+  a.flux = c->flux;
   return a;
 }
 
@@ -680,6 +702,7 @@ int tdg_residual_vjp_axpy(tdg_ctx* c, const void* U, const void* W, double cw, i
   int st = require_bound(c);
   if (st) return st;
   if (!U || !W || !Out || Out == U || Out == W) return fail(c, TDG_ERR_INVALID_ARG, "U, W, Out must be distinct");
+  if (c->flux != TDG_FLUX_RUSANOV) return fail(c, TDG_ERR_UNSUPPORTED, "the adjoint is implemented for the Rusanov flux");
   if (n_terms < 0 || n_terms > 3 || (n_terms > 0 && (!Y || !ya))) return fail(c, TDG_ERR_INVALID_ARG, "bad terms");
   VjpArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -705,6 +728,7 @@ int tdg_residual_vjp(tdg_ctx* c, const void* U, const void* W, void* Ubar, void*
   int st = require_bound(c);
   if (st) return st;
   if (!U || !W || !Ubar || Ubar == U || Ubar == W) return fail(c, TDG_ERR_INVALID_ARG, "U, W, Ubar must be distinct");
+  if (c->flux != TDG_FLUX_RUSANOV) return fail(c, TDG_ERR_UNSUPPORTED, "the adjoint is implemented for the Rusanov flux");
   VjpArgs a;
   std::memset(&a, 0, sizeof(a));
   a.c = 1.0;
@@ -726,6 +750,14 @@ int tdg_wall_pressure(tdg_ctx* c, const void* U, double* J, void* dJdU, void* s)
   if (!U || !J || (dJdU && dJdU == U)) return fail(c, TDG_ERR_INVALID_ARG, "bad pointers");
   hipError_t e = launch_wall_pressure(c->p, c->prec, view(c), refview(c), c->gamma, U, J, dJdU, (hipStream_t)s);
   return e == hipSuccess ? TDG_OK : hip_fail(c, e, "wall pressure launch");
+}
+
+int tdg_stable_dt(tdg_ctx* c, const void* U, double cfl, double* dt, void* s) {
+  int st = require_bound(c);
+  if (st) return st;
+  if (!U || !dt || !(cfl > 0.0)) return fail(c, TDG_ERR_INVALID_ARG, "bad arguments");
+  hipError_t e = launch_local_dt(c->p, c->prec, view(c), c->gamma, cfl, U, dt, (hipStream_t)s);
+  return e == hipSuccess ? TDG_OK : hip_fail(c, e, "stable dt launch");
 }
 
 int tdg_sync_check(tdg_ctx* c, void* s) {

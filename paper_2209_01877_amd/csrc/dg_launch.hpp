@@ -19,6 +19,7 @@ struct StageArgs {
   const double* mean_tab;  // mixed modes: the moments as fp64 MFMA A operands, [MT][2][64]
   double gamma;
   double far[5];      // farfield conserved state
+  int flux;           // 0 Rusanov, 1 Roe
   // mixed modes: low-precision operand companion of u_in (modes 1.. as bf16/fp16,
   // [E][5][32 KS]) and its fp32 cell means ([5][E]); the stage result's companion is
   // written to q_out / c0_out when they are non-null
@@ -62,6 +63,8 @@ hipError_t launch_get_state(int p, int prec, const MeshView& m, const void* inte
 hipError_t launch_volume_points(int p, const MeshView& m, const RefView& r, double* xyz, hipStream_t s);
 hipError_t launch_wall_pressure(int p, int prec, const MeshView& m, const RefView& r, double gamma, const void* u,
                                 double* J, void* grad, hipStream_t s);
+hipError_t launch_local_dt(int p, int prec, const MeshView& m, double gamma, double cfl, const void* u, double* dt,
+                           hipStream_t s);
 hipError_t launch_project(int p, int prec, const MeshView& m, const RefView& r, double gamma, const double* prim,
                           void* internal, hipStream_t s);
 

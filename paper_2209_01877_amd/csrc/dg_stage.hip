@@ -79,8 +79,15 @@ __device__ __forceinline__ void load_operands(const char* __restrict__ base, uin
   }
 }
 
+// Two workgroups per CU (two waves per SIMD, at most 256 registers per lane) where the
+// live state fits; fp64 and P4 keep one (their tables and operands need the registers).
+template <int P, class Pr>
+constexpr int stage_min_blocks() {
+  return (P <= 3 && !Pr::f64) ? 2 : 1;
+}
+
 template <int P, class Pr, bool kLds>
-__global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
+__global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel(StageArgs a) {
   using O = Ord<P>;
   using L = Layout<P, Pr::KW>;
   using S = typename Pr::S;
@@ -226,19 +233,17 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
           T ya[3][5], yb[3][5];
           point_flux(2 * jp, ya);
           point_flux(2 * jp + 1, yb);
-          Op b[5];
 #pragma unroll
-          for (int v = 0; v < 5; ++v)
+          for (int v = 0; v < 5; ++v) {
+            Op b;
 #pragma unroll
             for (int m = 0; m < 8; ++m) {
               const int dd = m & 3;
-              b[v][m] = (typename Pr::E1)(dd == 3 ? T(0) : (m < 4 ? ya[dd][v] : yb[dd][v]));
+              b[m] = (typename Pr::E1)(dd == 3 ? T(0) : (m < 4 ? ya[dd][v] : yb[dd][v]));
             }
 #pragma unroll
-          for (int mt = 0; mt < MT; ++mt) {
-            const Op av = tab[L::proj(mt, qt, jp) * 64 + lane];
-#pragma unroll
-            for (int v = 0; v < 5; ++v) acc[mt][v] = Pr::mfma(av, b[v], acc[mt][v]);
+            for (int mt = 0; mt < MT; ++mt)
+              acc[mt][v] = Pr::mfma(tab[L::proj(mt, qt, jp) * 64 + lane], b, acc[mt][v]);
           }
         }
       }
@@ -248,7 +253,13 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
 #pragma unroll 1
     for (int f = 0; f < 4; ++f) {
       T N[3];
-      face_normal<T>(f, Md, N);
+      if constexpr (Pr::mixed) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          N[c] = f == 0 ? (Mt[c] + Mt[3 + c] + Mt[6 + c]) : f == 1 ? -Mt[c] : f == 2 ? -Mt[3 + c] : -Mt[6 + c];
+      } else {
+        face_normal<T>(f, Md, N);
+      }
       const T nn = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
       const int nbf = f == 0 ? nbr[0] : f == 1 ? nbr[1] : f == 2 ? nbr[2] : nbr[3];
       const int fpl = (fcode >> (2 * f)) & 3;
@@ -265,7 +276,7 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
           c0n[v] = a.c0_in[v * epad + en];
         }
         if (nbf < 0) ghost_state<T>(-nbf, c0t, N, far, c0n);
-        rusanov_n<T>(c0t, c0n, N, nn, gamma, fhbar);
+        num_flux<T>(a.flux, c0t, c0n, N, nn, gamma, fhbar);
       } else {
         load_operands<Pr, NP, KS>(ubase, var_bytes, enoff, om, bn);
       }
@@ -278,7 +289,12 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
         for (int s = 0; s < KS; ++s) {
           const Op av = tab[L::trace(f, ft, s) * 64 + lane];
 #pragma unroll
-          for (int v = 0; v < 5; ++v) dm[v] = Pr::mfma(av, bc[v][s], dm[v]);
+          for (int v = 0; v < 5; ++v) {
+            Op own = bc[v][s];
+            if constexpr (Pr::mixed)
+              own = reinterpret_cast<const Op*>(a.q_in)[(((int64_t)e * 5 + v) * KS + s) * 4 + g];
+            dm[v] = Pr::mfma(av, own, dm[v]);
+          }
         }
         // neighbour trace B_{f+} c+: the table depends on the neighbour's local face f+, which
         // varies by column; for every f+ present in the 16 columns the B operand is masked to
@@ -307,7 +323,7 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
           }
           if (nbf < 0) ghost_state<T>(-nbf, um, N, far, up);
           if (q < NF) {
-            rusanov_n<T>(um, up, N, nn, gamma, fl);
+            num_flux<T>(a.flux, um, up, N, nn, gamma, fl);
           } else {
 #pragma unroll
             for (int v = 0; v < 5; ++v) fl[v] = Pr::mixed ? fhbar[v] : T(0);
@@ -328,16 +344,14 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
               for (int v = 0; v < 5; ++v) acc[mt][v] = Pr::mfma(av, Pr::op1(fh[v][lk]), acc[mt][v]);
             }
         } else {
-          Op b[5];
 #pragma unroll
-          for (int v = 0; v < 5; ++v)
+          for (int v = 0; v < 5; ++v) {
+            Op b;
 #pragma unroll
-            for (int m = 0; m < 8; ++m) b[v][m] = (typename Pr::E1)(m < 4 ? fh[v][m] : T(0));
+            for (int m = 0; m < 8; ++m) b[m] = (typename Pr::E1)(m < 4 ? fh[v][m] : T(0));
 #pragma unroll
-          for (int mt = 0; mt < MT; ++mt) {
-            const Op av = tab[L::lift(mt, f, ft, 0) * 64 + lane];
-#pragma unroll
-            for (int v = 0; v < 5; ++v) acc[mt][v] = Pr::mfma(av, b[v], acc[mt][v]);
+            for (int mt = 0; mt < MT; ++mt)
+              acc[mt][v] = Pr::mfma(tab[L::lift(mt, f, ft, 0) * 64 + lane], b, acc[mt][v]);
           }
         }
       }
@@ -351,6 +365,8 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
     // accumulator rows line up with the fp32 accumulator rows of the same lane.
     d4_t mean_acc[Pr::mixed ? MT : 1][5];
     if constexpr (Pr::mixed) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) Md[i] = mv.M[i * epad + e];
       double c0[5], x0[5], x1[5], yg[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) c0[v] = double(*reinterpret_cast<const S*>(ubase + (size_t)v * var_bytes + eoff));
@@ -383,7 +399,7 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
         } else {
           ghost_state<double>(-nbf, c0, N, far64, cn);
         }
-        rusanov_n<double>(c0, cn, N, nn, a.gamma, fb);
+        num_flux<double>(a.flux, c0, cn, N, nn, a.gamma, fb);
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
           x0[v] = g == 3 ? fb[v] : yg[v];

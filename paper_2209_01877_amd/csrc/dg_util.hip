@@ -103,6 +103,55 @@ __global__ void wall_pressure_kernel(MeshView m, int np, int nf, RefView r, doub
   if (Jloc != 0.0) atomicAdd(J, Jloc);
 }
 
+// Global minimum of the local explicit steps dt_K = cfl d_K / ((2p+1)(|u_K| + c_K)) over
+// the cell means, d_K = 6|K| / sum_f A_f (the paper's minimum of local time steps, here a
+// wavefront shuffle reduction per block and one atomic minimum on the bit pattern of a
+// positive double).
+__global__ void local_dt_kernel(MeshView m, int np, double gamma, double scale, const void* u, int f32,
+                                unsigned long long* out) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  double dt = 1e300;
+  if (e < m.n_elem) {
+    double U[5];
+    for (int v = 0; v < 5; ++v) {
+      const int64_t idx = (int64_t)(v * np) * m.epad + e;
+      U[v] = f32 ? double(((const float*)u)[idx]) : ((const double*)u)[idx];
+    }
+    const double ir = 1.0 / U[0];
+    const double q2 = (U[1] * U[1] + U[2] * U[2] + U[3] * U[3]) * ir * ir;
+    const double p = (gamma - 1.0) * (U[4] - 0.5 * U[0] * q2);
+    const double lam = sqrt(q2) + sqrt(gamma * p * ir);
+    double Mr[9], area2 = 0.0;
+    for (int k = 0; k < 9; ++k) Mr[k] = m.M[k * m.epad + e];
+    for (int f = 0; f < 4; ++f) {
+      double N[3];
+      for (int c = 0; c < 3; ++c)
+        N[c] = f == 0 ? (Mr[c] + Mr[3 + c] + Mr[6 + c]) : f == 1 ? -Mr[c] : f == 2 ? -Mr[3 + c] : -Mr[6 + c];
+      area2 += sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);  // 2 A_f
+    }
+    const double vol = 1.0 / m.inv_vol[e];
+    const double d = 12.0 * vol / area2;  // 6 |K| / sum A_f
+    dt = scale * d / lam;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_down(dt, off, 64);
+    dt = o < dt ? o : dt;
+  }
+  __shared__ double wmin[16];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) wmin[w] = dt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = wmin[0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) b = wmin[i] < b ? wmin[i] : b;
+    unsigned long long bits;
+    __builtin_memcpy(&bits, &b, 8);
+    atomicMin(out, bits);
+  }
+}
+
+__global__ void fill_u64_kernel(unsigned long long* p, unsigned long long v) { *p = v; }
+
 inline int np_of(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
@@ -137,14 +186,22 @@ hipError_t launch_volume_points(int p, const MeshView& m, const RefView& r, doub
 hipError_t launch_wall_pressure(int p, int prec, const MeshView& m, const RefView& r, double gamma, const void* u,
                                 double* J, void* grad, hipStream_t s) {
   const int np = np_of(p), nf = (p + 1) * (p + 1);
-  hipError_t e = hipMemsetAsync(J, 0, sizeof(double), s);
-  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(1), 0, s, (unsigned long long*)J, 0ULL);
   if (prec == 1)
     hipLaunchKernelGGL(wall_pressure_kernel<float>, dim3(nblocks(m.epad, 128)), dim3(128), 0, s, m, np, nf, r, gamma,
                        (const float*)u, J, (float*)grad);
   else
     hipLaunchKernelGGL(wall_pressure_kernel<double>, dim3(nblocks(m.epad, 128)), dim3(128), 0, s, m, np, nf, r,
                        gamma, (const double*)u, J, (double*)grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_local_dt(int p, int prec, const MeshView& m, double gamma, double cfl, const void* u, double* dt,
+                           hipStream_t s) {
+  // start from +inf (bit pattern 0x7ff0...); the first atomic minimum replaces it
+  hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(1), 0, s, (unsigned long long*)dt, 0x7ff0000000000000ULL);
+  hipLaunchKernelGGL(local_dt_kernel, dim3(nblocks(m.n_elem, 256)), dim3(256), 0, s, m, np_of(p), gamma,
+                     cfl / (2 * p + 1), u, prec == 1 ? 1 : 0, (unsigned long long*)dt);
   return hipGetLastError();
 }
 

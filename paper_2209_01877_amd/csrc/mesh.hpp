@@ -25,7 +25,9 @@ std::string build_topology(int64_t n, const int64_t* elem_vid, const double* ele
 std::string build_geometry(const HostMesh& m, std::vector<double>& M, std::vector<double>& inv_vol,
                            std::vector<double>& x0j);
 
-// Permutation new -> old.  mode: 0 identity, 1 RCM, 2 Morton, 3 Hilbert.
-std::vector<int64_t> renumber(const HostMesh& m, int mode);
+// Permutation new -> old.  mode: 0 identity, 1 RCM, 2 Morton, 3 Hilbert.  With
+// group_codes the RCM/curve order is refined by grouping equal neighbour face codes
+// inside windows of 256 elements.
+std::vector<int64_t> renumber(const HostMesh& m, int mode, bool group_codes);
 
 }  // namespace tetdg

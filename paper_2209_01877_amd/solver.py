@@ -88,14 +88,18 @@ class Solver:
         """Upload a synthetic.TetMesh."""
         return self.upload_mesh(mesh.elem_vid, mesh.elem_xyz, mesh.bface_vid, mesh.bface_tag, renumber, stream)
 
+    def set_flux(self, flux: str) -> None:
+        """'rusanov' (default) or 'roe'."""
+        check(lib.tdg_set_flux(self._ctx, {"rusanov": 0, "roe": 1}[flux]), self._ctx, "tdg_set_flux")
+
     def set_farfield(self, prim) -> None:
         arr = np.ascontiguousarray(prim, dtype=np.float64)
         check(lib.tdg_set_farfield(self._ctx, arr.ctypes.data), self._ctx)
 
     def mesh_stats(self) -> dict:
-        out = np.zeros(6, dtype=np.int64)
+        out = np.zeros(7, dtype=np.int64)
         check(lib.tdg_mesh_stats(self._ctx, out.ctypes.data), self._ctx)
-        keys = ["n_elem", "n_elem_pad", "interior_faces", "boundary_faces", "bandwidth", "near64"]
+        keys = ["n_elem", "n_elem_pad", "interior_faces", "boundary_faces", "bandwidth", "near64", "tile_tables"]
         return dict(zip(keys, out.tolist()))
 
     # ----------------------------------------------------------------- state
@@ -201,6 +205,14 @@ class Solver:
         check(lib.tdg_wall_pressure(self._ctx, _ptr(U), _ptr(J), None if g is None else ctypes.c_void_p(_ptr(g)),
                                     _stream(stream)), self._ctx, "tdg_wall_pressure")
         return (J, g) if grad else J
+
+    def stable_dt(self, U: torch.Tensor, cfl: float = 0.2, stream=None) -> torch.Tensor:
+        """min_K cfl d_K / ((2p+1)(|u_K| + c_K)) as a 0-d device tensor."""
+        self._check_state(U)
+        dt = torch.empty((), dtype=torch.float64, device=self.device)
+        check(lib.tdg_stable_dt(self._ctx, _ptr(U), float(cfl), _ptr(dt), _stream(stream)), self._ctx,
+              "tdg_stable_dt")
+        return dt
 
     def sync(self, stream=None) -> None:
         check(lib.tdg_sync_check(self._ctx, _stream(stream)), self._ctx, "tdg_sync_check")

@@ -65,7 +65,7 @@ def _upload(ctx, mesh, renumber=0, perm=None):
 
 
 def _stats(ctx):
-    out = np.zeros(6, np.int64)
+    out = np.zeros(7, np.int64)
     assert _lib.lib.tdg_mesh_stats(ctx, out.ctypes.data) == 0
     return out
 
@@ -142,7 +142,7 @@ def test_renumbering_reduces_bandwidth():
     magnitude (smallest reduction 1427 -> 69, about 20x).  The shuffled 24^3 x 6 mesh must get at
     least that factor from RCM, and the space-filling curves must keep most neighbours close."""
     m = kuhn_cube(24, shuffle_seed=2209, vid_seed=2210)
-    ctx = _ctx(1)
+    ctx = _ctx(1, prec=2)  # mixed mode: plain orders
     out = {}
     for mode in ["none", "rcm", "morton", "hilbert"]:
         assert _upload(ctx, m, RENUMBER[mode]) == 0
@@ -151,4 +151,13 @@ def test_renumbering_reduces_bandwidth():
     assert out["none"][4] / out["rcm"][4] >= 20.7
     assert out["morton"][5] > 0.5 * pairs and out["hilbert"][5] > 0.5 * pairs
     assert out["none"][5] < 0.01 * pairs
+    _lib.lib.tdg_destroy(ctx)
+    # fp64 mode: RCM keeps the bandwidth reduction after the face-code grouping, and the
+    # grouping lowers the number of neighbour face tables per tile
+    ctx = _ctx(1, prec=0)
+    assert _upload(ctx, m, RENUMBER["rcm"]) == 0
+    assert out["none"][4] / _stats(ctx)[4] >= 20.7
+    assert _upload(ctx, m, RENUMBER["hilbert"]) == 0
+    grouped = _stats(ctx)
+    assert grouped[6] < 0.75 * out["hilbert"][6]
     _lib.lib.tdg_destroy(ctx)

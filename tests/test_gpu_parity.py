@@ -135,3 +135,54 @@ def test_deterministic():
     a = gpu_residual(s, U)
     b = gpu_residual(s, U)
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_stable_dt(prec):
+    """GPU minimum of the local time steps against the oracle's."""
+    mesh = make_mesh("ragged")
+    dg = oracle(2, mesh)
+    U = random_state(dg, seed=13)
+    s = solver(2, prec, mesh)
+    dt = s.stable_dt(s.set_state(U.cuda()), cfl=0.3).item()
+    ref = dg.local_dt_min(U, cfl=0.3)
+    assert abs(dt - ref) < (1e-14 if prec != "fp32" else 1e-6) * ref
+
+
+@pytest.mark.parametrize("p", [1, 3])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("kind", ["ragged", "bump"])
+def test_roe_flux(p, prec, kind):
+    """The paper's Roe interface flux as an option, against the oracle's Roe flux."""
+    from oracle.dg import DG
+
+    far = (1.0, 0.5 * math.sqrt(1.4), 0.0, 0.0, 1.0)
+    mesh = make_mesh(kind)
+    dg = DG(p, mesh.elem_vid, mesh.elem_xyz, mesh.bface_vid, mesh.bface_tag, farfield_prim=far, flux="roe")
+    U = random_state(dg, seed=17)
+    s = solver(p, prec, mesh, farfield=far)
+    s.set_flux("roe")
+    err = rel_err(dg, gpu_residual(s, U), dg.residual(U))
+    print(f"roe p={p} {prec} {kind}: rel L2 error {err:.3e}")
+    assert err < TOL[prec]
+
+
+def test_temporal_mixed_precision():
+    """MP-N: the first N steps in fp32, the rest in fp64.  N = 0 is exactly the fp64 run; the
+    deviation from the fp64 run stays at fp32 rounding and does not grow with fewer fp32 steps."""
+    from paper_2209_01877_amd.schedule import TemporalMixed
+
+    mesh = make_mesh("jitter4")
+    dg = oracle(2, mesh)
+    U0 = dg.project(lambda z: fields.isentropic_vortex(z, length=1.0, beta=0.5)).cuda()
+    dt = 0.5 * dg.stable_dt(U0.cpu())
+    tm = TemporalMixed(2, mesh)
+    ref = tm.run(U0, dt, 0, 20)
+    plain = solver(2, "fp64", mesh)
+    Ui = plain.set_state(U0)
+    plain.rk_step(Ui, dt, 20)
+    assert torch.equal(plain.get_state(Ui), ref)
+    errs = [((tm.run(U0, dt, n, 20) - ref).norm() / (ref - U0).norm()).item() for n in (5, 10, 20)]
+    print("MP errors vs fp64 (relative to the change of the state):", errs)
+    assert all(e < 1e-4 for e in errs)
+    assert errs[0] <= errs[2] * 1.5

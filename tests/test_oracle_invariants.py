@@ -196,3 +196,46 @@ def test_wall_pressure_uniform_state():
         a, b, c = [X[v] for v in range(4) if v != f]
         area += 0.5 * np.linalg.norm(np.cross(b - a, c - a))
     assert abs(dg.wall_pressure(U).item() - 0.8 * area) < 1e-13 * area
+
+
+def test_local_dt_min_uniform_state():
+    """For a uniform state every local step uses the same wave speed, so the minimum of the
+    local steps equals the global formula cfl min d_K / ((2p+1) max(|u| + c))."""
+    dg = _dg(2, 4, jitter=0.2)
+    U = dg.project(lambda x: fields.freestream(x, 1.0, (0.3, -0.2, 0.5), 1.0))
+    assert abs(dg.local_dt_min(U, 0.2) - dg.stable_dt(U, 0.2)) < 1e-14 * dg.stable_dt(U, 0.2)
+
+
+def test_roe_flux_properties():
+    """Roe flux: consistency F(U, U) = F(U).n; supersonic flow (all waves moving out of the
+    minus side, u.n > c + entropy-fix width) reduces to the upwind flux F(U-).n; Roe's
+    property F(U+) - F(U-) = A_roe (U+ - U-) appears as antisymmetry of the jump term."""
+    g = 1.4
+    rng = np.random.default_rng(0)
+    n = torch.from_numpy(rng.standard_normal((50, 3)))
+    n = n / n.norm(dim=1, keepdim=True)
+    prim_a = torch.from_numpy(np.c_[rng.uniform(0.8, 1.2, 50), rng.uniform(-0.3, 0.3, (50, 3)), rng.uniform(0.8, 1.2, 50)])
+    prim_b = torch.from_numpy(np.c_[rng.uniform(0.8, 1.2, 50), rng.uniform(-0.3, 0.3, (50, 3)), rng.uniform(0.8, 1.2, 50)])
+    a = euler.prim_to_cons(prim_a, g)
+    b = euler.prim_to_cons(prim_b, g)
+    assert torch.allclose(euler.roe(a, a, n, g), euler.normal_flux(a, n, g), atol=1e-14, rtol=0)
+    # flux from the other side with the opposite normal is the negative
+    assert torch.allclose(euler.roe(a, b, n, g), -euler.roe(b, a, -n, g), atol=1e-13, rtol=0)
+    # supersonic along n: add 3.0 n to both velocities
+    pa, pb = prim_a.clone(), prim_b.clone()
+    pa[:, 1:4] += 3.0 * n
+    pb[:, 1:4] += 3.0 * n
+    a, b = euler.prim_to_cons(pa, g), euler.prim_to_cons(pb, g)
+    assert torch.allclose(euler.roe(a, b, n, g), euler.normal_flux(a, n, g), atol=1e-12, rtol=0)
+
+
+def test_roe_free_stream_and_conservation():
+    m = kuhn_cube(4, jitter=0.2, shuffle_seed=2209, vid_seed=2210)
+    dg = DG(2, m.elem_vid, m.elem_xyz, flux="roe")
+    U = dg.project(lambda x: fields.freestream(x, 1.0, (0.3, -0.2, 0.5), 1.0))
+    assert dg.residual(U).abs().max() < 1e-11
+    U = torch.from_numpy(fields.random_coefficients(dg.n_elem, dg.Np, seed=11, scale=0.01))
+    R = dg.residual(U)
+    total = (dg.volume[:, None] * R[:, :, 0]).sum(0)
+    scale = (dg.volume[:, None] * R[:, :, 0].abs()).sum(0)
+    assert (total.abs() <= 1e-13 * scale).all()
