@@ -140,8 +140,10 @@ int tdg_mesh_stats(const tdg_ctx* ctx, int64_t out[7]);
 
 /* ------------------------------------------------------------------ state */
 
-/* Internal state: [5][N_p][n_elem_pad] in renumbered element order (element index
- * fastest), double for TDG_FP64 and the mixed modes, float for TDG_FP32.
+/* Internal state: [5][ceil(N_p/4)][n_elem_pad][4] in renumbered element order: for each
+ * variable, quads of four consecutive modes, element index next, the four modes of a quad
+ * innermost (modes past N_p are padding, written as zero by set_state/project).  double for
+ * TDG_FP64 and the mixed modes, float for TDG_FP32.
  * User state:     [n_elem][5][N_p] double, caller's element order. */
 int tdg_state_elems(const tdg_ctx* ctx, int64_t* n_elem_pad);
 int tdg_state_bytes(const tdg_ctx* ctx, size_t* bytes);

@@ -9,7 +9,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libtetdg.so")
+# TETDG_LIBRARY selects another build of the same library (e.g. one compiled with
+# different options); by default the in-tree build is loaded.
+LIB_PATH = os.environ.get("TETDG_LIBRARY") or os.path.join(HERE, "libtetdg.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libtetdg.so not found at {LIB_PATH}; build it with paper_2209_01877_amd/build.py "

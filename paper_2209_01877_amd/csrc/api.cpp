@@ -292,7 +292,7 @@ int require_bound(tdg_ctx* c) {
 }
 
 size_t state_bytes(const tdg_ctx* c) {
-  return (size_t)5 * c->ref.np * c->epad * (c->prec == TDG_FP32 ? sizeof(float) : sizeof(double));
+  return (size_t)5 * 4 * npq_of(c->ref.np) * c->epad * (c->prec == TDG_FP32 ? sizeof(float) : sizeof(double));
 }
 
 bool is_mixed(const tdg_ctx* c) { return c->prec >= TDG_MIXED_BF16; }
@@ -376,6 +376,9 @@ int tdg_mesh_upload(tdg_ctx* c, int64_t n_elem, const int64_t* elem_vid, const d
     std::vector<int64_t> inv(n_elem);
     for (int64_t i = 0; i < n_elem; ++i) inv[order[i]] = i;
     const int64_t epad = (n_elem + 63) / 64 * 64;
+    const double var_bytes = 4.0 * npq_of(c->ref.np) * (double)epad * (c->prec == TDG_FP32 ? 4 : 8);
+    if (var_bytes >= 4294967296.0)
+      return fail(c, TDG_ERR_UNSUPPORTED, "mesh too large: one variable of the state exceeds 4 GiB (32-bit offsets)");
     c->n = n_elem;
     c->epad = epad;
     c->n_interior = hm.n_interior;

@@ -83,6 +83,15 @@ struct VjpLayout {
   }
 };
 
+// Internal state layout: [5 variables][ceil(N_p / 4) mode quads][epad elements][4 modes].
+// Four consecutive modes of one element are contiguous, so the four lane groups of an
+// MFMA column (which hold modes 4s .. 4s+3 of one element) read one 32-byte run, and a
+// neighbour's coefficients touch a quarter of the cache lines of a plain plane layout.
+inline constexpr int npq_of(int np) { return (np + 3) / 4; }
+__host__ __device__ inline int64_t sidx(int v, int mode, int64_t e, int64_t epad, int npq) {
+  return (((int64_t)v * npq + (mode >> 2)) * epad + e) * 4 + (mode & 3);
+}
+
 // Device mesh view (structure of arrays, element index fastest, padded length epad).
 struct MeshView {
   const double* M;       // [9][epad]  |det J| J^-1, row-major 3x3

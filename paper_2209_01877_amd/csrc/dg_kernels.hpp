@@ -76,22 +76,34 @@ __device__ __forceinline__ float prec_sqrt(float x) { return __builtin_amdgcn_sq
 __device__ __forceinline__ double prec_sqrt(double x) { return sqrt(x); }
 
 // ---------------------------------------------------------------- Euler physics
+// The pointwise physics is written with explicit fused multiply-adds and compiled without
+// letting the compiler contract any other product into a sum: every inlined copy of a
+// function then rounds identically, so a point whose state equals the cell mean reproduces
+// the cell-mean flux bit for bit (the mixed modes rely on this for exact free-stream
+// preservation).  Two-sided sums in the face fluxes add one-sided terms, which keeps the
+// flux exactly antisymmetric under exchanging the two states and negating the normal.
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // Contravariant flux rows y_d = sum_e M[d][e] F_e(U) for d = 0..2, where F_e is the
-// Euler flux in direction e (eq. 2, 3-D) and M = |det J| J^-1.
+// Euler flux in direction e (eq. 2, 3-D) and M = |det J| J^-1:
+//   theta_d = M_d . v,  y_d = (rho theta_d, m theta_d + p M_d, (E + p) theta_d).
 template <class T>
 __device__ __forceinline__ void contra_flux(const T u[5], const T M[9], T gm1, T y[3][5]) {
+#pragma clang fp contract(off)
   const T rho = u[0];
   const T ir = prec_rcp(rho);
   const T vx = u[1] * ir, vy = u[2] * ir, vz = u[3] * ir;
-  const T p = gm1 * (u[4] - T(0.5) * (u[1] * vx + u[2] * vy + u[3] * vz));
+  const T mv = fmaT(u[1], vx, fmaT(u[2], vy, u[3] * vz));
+  const T p = gm1 * fmaT(T(-0.5), mv, u[4]);
   const T ep = u[4] + p;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const T th = M[3 * d + 0] * vx + M[3 * d + 1] * vy + M[3 * d + 2] * vz;
+    const T th = fmaT(M[3 * d + 0], vx, fmaT(M[3 * d + 1], vy, M[3 * d + 2] * vz));
     y[d][0] = rho * th;
-    y[d][1] = u[1] * th + p * M[3 * d + 0];
-    y[d][2] = u[2] * th + p * M[3 * d + 1];
-    y[d][3] = u[3] * th + p * M[3 * d + 2];
+    y[d][1] = fmaT(u[1], th, p * M[3 * d + 0]);
+    y[d][2] = fmaT(u[2], th, p * M[3 * d + 1]);
+    y[d][3] = fmaT(u[3], th, p * M[3 * d + 2]);
     y[d][4] = ep * th;
   }
 }
@@ -100,21 +112,25 @@ __device__ __forceinline__ void contra_flux(const T u[5], const T M[9], T gm1, T
 //   Fhat = (F(um).N + F(up).N)/2 - max(|um.N| + c- nn, |up.N| + c+ nn)/2 (up - um)
 template <class T>
 __device__ __forceinline__ void rusanov_n(const T um[5], const T up[5], const T N[3], T nn, T gamma, T out[5]) {
+#pragma clang fp contract(off)
   const T gm1 = gamma - T(1);
   const T irm = prec_rcp(um[0]), irp = prec_rcp(up[0]);
-  const T unm = (um[1] * N[0] + um[2] * N[1] + um[3] * N[2]) * irm;
-  const T unp = (up[1] * N[0] + up[2] * N[1] + up[3] * N[2]) * irp;
-  const T pm = gm1 * (um[4] - T(0.5) * (um[1] * um[1] + um[2] * um[2] + um[3] * um[3]) * irm);
-  const T pp = gm1 * (up[4] - T(0.5) * (up[1] * up[1] + up[2] * up[2] + up[3] * up[3]) * irp);
+  const T unm = fmaT(um[1], N[0], fmaT(um[2], N[1], um[3] * N[2])) * irm;
+  const T unp = fmaT(up[1], N[0], fmaT(up[2], N[1], up[3] * N[2])) * irp;
+  const T km = fmaT(um[1], um[1], fmaT(um[2], um[2], um[3] * um[3]));
+  const T kp = fmaT(up[1], up[1], fmaT(up[2], up[2], up[3] * up[3]));
+  const T pm = gm1 * fmaT(T(-0.5) * km, irm, um[4]);
+  const T pp = gm1 * fmaT(T(-0.5) * kp, irp, up[4]);
   const T cm = prec_sqrt(gamma * pm * irm), cp = prec_sqrt(gamma * pp * irp);
-  const T lm = fabs(unm) + cm * nn, lp = fabs(unp) + cp * nn;
-  const T lam = lm > lp ? lm : lp;
+  const T lm = fmaT(cm, nn, fabs(unm)), lp = fmaT(cp, nn, fabs(unp));
+  const T hl = T(0.5) * (lm > lp ? lm : lp);
   const T h = T(0.5);
-  out[0] = h * (um[0] * unm + up[0] * unp) - h * lam * (up[0] - um[0]);
+  out[0] = fmaT(h, um[0] * unm + up[0] * unp, -(hl * (up[0] - um[0])));
 #pragma unroll
   for (int d = 0; d < 3; ++d)
-    out[1 + d] = h * (um[1 + d] * unm + pm * N[d] + up[1 + d] * unp + pp * N[d]) - h * lam * (up[1 + d] - um[1 + d]);
-  out[4] = h * ((um[4] + pm) * unm + (up[4] + pp) * unp) - h * lam * (up[4] - um[4]);
+    out[1 + d] = fmaT(h, fmaT(um[1 + d], unm, pm * N[d]) + fmaT(up[1 + d], unp, pp * N[d]),
+                      -(hl * (up[1 + d] - um[1 + d])));
+  out[4] = fmaT(h, (um[4] + pm) * unm + (up[4] + pp) * unp, -(hl * (up[4] - um[4])));
 }
 
 // Roe flux through an area-weighted normal N (|N| = nn): central part minus
@@ -122,6 +138,7 @@ __device__ __forceinline__ void rusanov_n(const T um[5], const T up[5], const T 
 // waves u.n -+ c (Harten entropy fix of width 0.1 c), entropy and shear waves at u.n.
 template <class T>
 __device__ __forceinline__ void roe_n(const T um[5], const T up[5], const T N[3], T nn, T gamma, T out[5]) {
+#pragma clang fp contract(off)
   const T gm1 = gamma - T(1);
   const T inn = prec_rcp(nn);
   const T n[3] = {N[0] * inn, N[1] * inn, N[2] * inn};
@@ -188,6 +205,7 @@ __device__ __forceinline__ void num_flux(int kind, const T um[5], const T up[5],
 // (density and energy kept, normal momentum mirrored).
 template <class T>
 __device__ __forceinline__ void ghost_state(int tag, const T um[5], const T N[3], const T far[5], T up[5]) {
+#pragma clang fp contract(off)
   if (tag == 2) {
     const T nn2 = N[0] * N[0] + N[1] * N[1] + N[2] * N[2];
     const T mn = (um[1] * N[0] + um[2] * N[1] + um[3] * N[2]) * prec_rcp(nn2);

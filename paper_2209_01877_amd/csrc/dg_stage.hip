@@ -24,8 +24,14 @@
 // every quantity into its cell-mean part and a deviation: phi_0 = 1, so the
 // mean coefficient c_0 is added in fp32 after the low-precision contraction of
 // c_1..; the pointwise fluxes enter the projections as deviations from the flux
-// of the cell means, whose own projection uses fp64 moments in the epilogue.
-// A uniform state therefore gives exactly zero deviation terms.
+// of the cell means, whose own projection uses fp64 moments in the epilogue.  The
+// pointwise fluxes round identically at every call site (explicit fused multiply-adds
+// only), so a point whose state equals the cell mean gives exactly zero deviation: a
+// uniform state keeps its residual at fp64 round-off.
+//
+// Latency: the neighbour operands of face 0 are requested before the volume integral
+// and those of face f + 1 as soon as face f's neighbour trace has consumed its own, so
+// the face phase waits on no memory; the epilogue issues all reads of a mode tile at once.
 #include <hip/hip_runtime.h>
 
 #include "dg_kernels.hpp"
@@ -41,14 +47,15 @@ namespace tetdg {
 template <class Pr, int NP, int KS>
 struct OperandMap {
   static constexpr int NV = Pr::KW == 1 ? KS : 8 * KS;  // loads per variable
-  uint32_t off[NV];                                     // plane offset, bytes
+  uint32_t off[NV];                                     // mode offset within a variable, bytes
   bool keep[NV];
-  __device__ void init(int g, uint32_t plane_bytes) {
+  __device__ void init(int g, uint32_t quad_bytes) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       const int mode = Pr::KW == 1 ? 4 * i + g : 32 * (i / 8) + 8 * g + (i % 8);
+      const int mc = mode < NP ? mode : NP - 1;
       keep[i] = mode < NP && !(Pr::mixed && mode == 0);
-      off[i] = (uint32_t)(mode < NP ? mode : NP - 1) * plane_bytes;
+      off[i] = (uint32_t)(mc >> 2) * quad_bytes + (uint32_t)(mc & 3) * sizeof(typename Pr::S);
     }
   }
 };
@@ -81,6 +88,18 @@ __device__ __forceinline__ void load_operands(const char* __restrict__ base, uin
 
 // Two workgroups per CU (two waves per SIMD, at most 256 registers per lane) where the
 // live state fits; fp64 and P4 keep one (their tables and operands need the registers).
+// Packed pair of operand-precision values (KW = 8 modes); a placeholder otherwise.
+template <class Pr, bool = (Pr::KW == 8)>
+struct LiftPair {
+  using E1 = float;
+  typedef float type __attribute__((ext_vector_type(2)));
+};
+template <class Pr>
+struct LiftPair<Pr, true> {
+  using E1 = typename Pr::E1;
+  typedef E1 type __attribute__((ext_vector_type(2)));
+};
+
 template <int P, class Pr>
 constexpr int stage_min_blocks() {
   return (P <= 3 && !Pr::f64) ? 2 : 1;
@@ -111,8 +130,9 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
   const char* __restrict__ ubase = reinterpret_cast<const char*>(a.u_in);
   const MeshView& mv = a.mesh;
   const int64_t epad = mv.epad;
-  const uint32_t plane = (uint32_t)(epad * sizeof(S));  // bytes of one (variable, mode) plane
-  const uint32_t var_bytes = plane * NP;
+  constexpr int NPQ = npq_of(NP);
+  const uint32_t quad_bytes = (uint32_t)(epad * 4 * sizeof(S));  // one (variable, mode quad) plane
+  const uint32_t var_bytes = quad_bytes * NPQ;
   const T gamma = T(a.gamma), gm1 = T(a.gamma - 1.0);
   T far[5];
   double far64[5];
@@ -122,7 +142,7 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
     far[v] = T(a.far[v]);
   }
   OperandMap<Pr, NP, KS> om;
-  om.init(g, plane);
+  om.init(g, quad_bytes);
 
   // Work distribution: workgroups are dispatched round-robin over the 8 XCDs, so block b
   // runs on XCD b % 8.  Each XCD owns one contiguous eighth of the 16-element groups and
@@ -142,7 +162,7 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
 
   for (int64_t grp = g_begin + wave_x; grp < g_end; grp += waves_x) {
     const int e = (int)(grp * 16 + col);
-    const uint32_t eoff = (uint32_t)e * sizeof(S);
+    const uint32_t eoff = (uint32_t)e * 4 * sizeof(S);
     double Md[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) Md[i] = mv.M[i * epad + e];
@@ -164,10 +184,29 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
         for (int s = 0; s < KS; ++s) bc[v][s] = q[(((int64_t)e * 5 + v) * KS + s) * 4 + g];
         c0t[v] = a.c0_in[v * epad + e];
       }
-      contra_flux<T>(c0t, Mt, gm1, ybar);
     } else {
       load_operands<Pr, NP, KS>(ubase, var_bytes, eoff, om, bc);
     }
+    // operands of the neighbour across face f (the element itself on a boundary face)
+    auto load_nbr = [&](int f, Op (&bx)[5][KS], T (&cx)[5]) {
+      const int nbf = f == 0 ? nbr[0] : f == 1 ? nbr[1] : f == 2 ? nbr[2] : nbr[3];
+      const int en = nbf >= 0 ? nbf : e;
+      if constexpr (Pr::mixed) {
+        const Op* q = reinterpret_cast<const Op*>(a.q_in);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+#pragma unroll
+          for (int s = 0; s < KS; ++s) bx[v][s] = q[(((int64_t)en * 5 + v) * KS + s) * 4 + g];
+          cx[v] = a.c0_in[v * epad + en];
+        }
+      } else {
+        load_operands<Pr, NP, KS>(ubase, var_bytes, (uint32_t)en * 4 * sizeof(S), om, bx);
+      }
+    };
+    Op bn[5][KS];
+    T c0n[5];
+    load_nbr(0, bn, c0n);
+    if constexpr (Pr::mixed) contra_flux<T>(c0t, Mt, gm1, ybar);
 
     Acc acc[MT][5];
 #pragma unroll
@@ -204,13 +243,10 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
         if constexpr (Pr::mixed) {
           // a point carrying exactly the cell mean has zero deviation (independent of how
           // the compiler schedules the two flux evaluations)
-          bool mean = true;
-#pragma unroll
-          for (int v = 0; v < 5; ++v) mean = mean && (u[v] == c0t[v]);
 #pragma unroll
           for (int dd = 0; dd < 3; ++dd)
 #pragma unroll
-            for (int v = 0; v < 5; ++v) yy[dd][v] = mean ? T(0) : yy[dd][v] - ybar[dd][v];
+            for (int v = 0; v < 5; ++v) yy[dd][v] -= ybar[dd][v];
         }
       };
       if constexpr (Pr::KW == 1) {
@@ -252,6 +288,7 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
     // ------------------------------------------------------------ face integrals
 #pragma unroll 1
     for (int f = 0; f < 4; ++f) {
+      T c0nn[5];
       T N[3];
       if constexpr (Pr::mixed) {
 #pragma unroll
@@ -263,39 +300,28 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
       const T nn = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
       const int nbf = f == 0 ? nbr[0] : f == 1 ? nbr[1] : f == 2 ? nbr[2] : nbr[3];
       const int fpl = (fcode >> (2 * f)) & 3;
-      const int en = nbf >= 0 ? nbf : e;
-      const uint32_t enoff = (uint32_t)en * sizeof(S);
-      Op bn[5][KS];
-      T c0n[5], fhbar[5];
+      T fhbar[5];
       if constexpr (Pr::mixed) {
-        const Op* q = reinterpret_cast<const Op*>(a.q_in);
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-#pragma unroll
-          for (int s = 0; s < KS; ++s) bn[v][s] = q[(((int64_t)en * 5 + v) * KS + s) * 4 + g];
-          c0n[v] = a.c0_in[v * epad + en];
-        }
         if (nbf < 0) ghost_state<T>(-nbf, c0t, N, far, c0n);
         num_flux<T>(a.flux, c0t, c0n, N, nn, gamma, fhbar);
-      } else {
-        load_operands<Pr, NP, KS>(ubase, var_bytes, enoff, om, bn);
       }
 #pragma unroll 1
       for (int ft = 0; ft < FT; ++ft) {
         Acc dm[5], dp[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v) dm[v] = dp[v] = Acc{0, 0, 0, 0};
+        // own trace B_f c (the mixed modes re-read their operands, which are then
+        // consumed after the neighbour trace so that the read latency is covered)
+        Op own[5][KS];
 #pragma unroll
-        for (int s = 0; s < KS; ++s) {
-          const Op av = tab[L::trace(f, ft, s) * 64 + lane];
+        for (int v = 0; v < 5; ++v)
 #pragma unroll
-          for (int v = 0; v < 5; ++v) {
-            Op own = bc[v][s];
+          for (int s = 0; s < KS; ++s) {
             if constexpr (Pr::mixed)
-              own = reinterpret_cast<const Op*>(a.q_in)[(((int64_t)e * 5 + v) * KS + s) * 4 + g];
-            dm[v] = Pr::mfma(av, own, dm[v]);
+              own[v][s] = reinterpret_cast<const Op*>(a.q_in)[(((int64_t)e * 5 + v) * KS + s) * 4 + g];
+            else
+              own[v][s] = bc[v][s];
           }
-        }
         // neighbour trace B_{f+} c+: the table depends on the neighbour's local face f+, which
         // varies by column; for every f+ present in the 16 columns the B operand is masked to
         // the columns having that f+, so all candidates accumulate into one result
@@ -311,7 +337,20 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
             }
           }
         }
-        T fh[5][4];
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          const Op av = tab[L::trace(f, ft, s) * 64 + lane];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) dm[v] = Pr::mfma(av, own[v][s], dm[v]);
+        }
+        // the neighbour operands are consumed: request the next face's while this face's
+        // own trace, fluxes and lifting are computed
+        if (f < 3 && ft == FT - 1) load_nbr(f + 1, bn, c0nn);
+        // face flux (deviation) at the tile's points: fp32 values for KW = 1, packed operand
+        // pairs for KW = 8 (the lift's B operand holds the four points in k = 8 g + 0..3)
+        T fh[5][Pr::KW == 1 ? 4 : 1];
+        typedef typename LiftPair<Pr>::type e2_t;
+        e2_t fhp[5][2];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int q = 16 * ft + drow_of<Pr>(g, j);
@@ -328,11 +367,14 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
 #pragma unroll
             for (int v = 0; v < 5; ++v) fl[v] = Pr::mixed ? fhbar[v] : T(0);
           }
-          bool mean = Pr::mixed;
 #pragma unroll
-          for (int v = 0; v < 5; ++v) mean = mean && (um[v] == c0t[v]) && (up[v] == c0n[v]);
-#pragma unroll
-          for (int v = 0; v < 5; ++v) fh[v][j] = Pr::mixed ? (mean ? T(0) : fl[v] - fhbar[v]) : fl[v];
+          for (int v = 0; v < 5; ++v) {
+            const T x = Pr::mixed ? fl[v] - fhbar[v] : fl[v];
+            if constexpr (Pr::KW == 1)
+              fh[v][j] = x;
+            else
+              fhp[v][j >> 1][j & 1] = (typename LiftPair<Pr>::E1)x;
+          }
         }
         if constexpr (Pr::KW == 1) {
 #pragma unroll
@@ -348,12 +390,16 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
           for (int v = 0; v < 5; ++v) {
             Op b;
 #pragma unroll
-            for (int m = 0; m < 8; ++m) b[m] = (typename Pr::E1)(m < 4 ? fh[v][m] : T(0));
+            for (int m = 0; m < 8; ++m) b[m] = m < 4 ? fhp[v][m >> 1][m & 1] : (typename Pr::E1)0.0f;
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
               acc[mt][v] = Pr::mfma(tab[L::lift(mt, f, ft, 0) * 64 + lane], b, acc[mt][v]);
           }
         }
+      }
+      if (f < 3) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) c0n[v] = c0nn[v];
       }
     }
 
@@ -363,91 +409,142 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
     // tile.  Lane group g supplies k = g (volume direction g, or face 0 for g = 3) and
     // k = 4 + g (face g + 1, or zero); the table rows are permuted so that the fp64
     // accumulator rows line up with the fp32 accumulator rows of the same lane.
-    d4_t mean_acc[Pr::mixed ? MT : 1][5];
+    // Every lane takes part in the epilogue's MFMAs (the A operand rows are spread over
+    // all lanes); only the stores are limited to the mesh's elements.
+    const bool live = e < mv.n_elem;
+    const char* u0base = reinterpret_cast<const char*>(a.u0);
+    char* obase = reinterpret_cast<char*>(a.u_out);
+    const bool comp = Pr::mixed && a.q_out != nullptr;
+    typedef S s4_t __attribute__((ext_vector_type(4)));
+    // fp64 data of the cell-mean fluxes (mixed modes)
+    double Me[Pr::mixed ? 9 : 1], c0e[Pr::mixed ? 5 : 1], c0g[Pr::mixed ? 5 : 1];
+    const int fg = g == 3 ? 0 : g + 1;
+    const int ng = fg == 0 ? nbr[0] : fg == 1 ? nbr[1] : fg == 2 ? nbr[2] : nbr[3];
     if constexpr (Pr::mixed) {
 #pragma unroll
-      for (int i = 0; i < 9; ++i) Md[i] = mv.M[i * epad + e];
-      double c0[5], x0[5], x1[5], yg[5];
+      for (int i = 0; i < 9; ++i) Me[i] = mv.M[i * epad + e];
+      const uint32_t goff = (uint32_t)(ng >= 0 ? ng : e) * 4 * sizeof(S);
 #pragma unroll
-      for (int v = 0; v < 5; ++v) c0[v] = double(*reinterpret_cast<const S*>(ubase + (size_t)v * var_bytes + eoff));
+      for (int v = 0; v < 5; ++v) {
+        c0e[v] = double(*reinterpret_cast<const S*>(ubase + (size_t)v * var_bytes + eoff));
+        c0g[v] = double(*reinterpret_cast<const S*>(ubase + (size_t)v * var_bytes + goff));
+      }
+    }
+    // State values of mode tile mt (mode = 16 mt + drow(g, j)): with the fp32 accumulator
+    // layout they form one mode quad per lane (one vector access); with the fp64 layout
+    // they sit at position g of four quads.  Padding modes of the last quad are written 0.
+    double uin[5][4], u0v[5][4];
+    auto load_tile = [&](int mt) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) uin[v][j] = u0v[v][j] = 0.0;
+      if (!a.rk || !live) return;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        const size_t vo = (size_t)v * var_bytes + eoff;
+        if constexpr (!Pr::f64) {
+          const int qd = 4 * mt + g;
+          if (qd < NPQ) {
+            const s4_t x = *reinterpret_cast<const s4_t*>(ubase + vo + (size_t)qd * quad_bytes);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) uin[v][j] = double(x[j]);
+            if (a.alpha != 0.0) {
+              const s4_t y = *reinterpret_cast<const s4_t*>(u0base + vo + (size_t)qd * quad_bytes);
+#pragma unroll
+              for (int j = 0; j < 4; ++j) u0v[v][j] = double(y[j]);
+            }
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int qd = 4 * mt + j;
+            if (qd < NPQ) {
+              const size_t o = vo + (size_t)qd * quad_bytes + (size_t)g * sizeof(S);
+              uin[v][j] = double(*reinterpret_cast<const S*>(ubase + o));
+              if (a.alpha != 0.0) u0v[v][j] = double(*reinterpret_cast<const S*>(u0base + o));
+            }
+          }
+        }
+      }
+    };
+
+    // mixed: fp64 projection of the cell-mean fluxes, sum_k mom_k[i] Fbar_k with the three
+    // volume directions and the four faces (k = 0..6), as two fp64 MFMA k-steps per mode
+    // tile.  Lane group g supplies k = g (volume direction g, or face 0 for g = 3) and
+    // k = 4 + g (face g + 1, or zero); the table rows are permuted so that the fp64
+    // accumulator rows line up with the fp32 accumulator rows of the same lane.
+    double x0[Pr::mixed ? 5 : 1], x1[Pr::mixed ? 5 : 1];
+    if constexpr (Pr::mixed) {
+      double yg[5];
       {
-        // contravariant mean flux in direction min(g, 2) only: blend the row of M arithmetically
-        // (a select chain would be turned into an indexed, stack-resident array)
+        // contravariant mean flux in direction min(g, 2) only: blend the row of M
+        // arithmetically (a select chain would become an indexed, stack-resident array)
         const double w0 = g == 0 ? 1.0 : 0.0, w1 = g == 1 ? 1.0 : 0.0, w2 = g >= 2 ? 1.0 : 0.0;
         double Mrow[9];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          Mrow[c] = w0 * Md[c] + w1 * Md[3 + c] + w2 * Md[6 + c];
+          Mrow[c] = w0 * Me[c] + w1 * Me[3 + c] + w2 * Me[6 + c];
           Mrow[3 + c] = 0.0;
           Mrow[6 + c] = 0.0;
         }
         double y3[3][5];
-        contra_flux<double>(c0, Mrow, a.gamma - 1.0, y3);
+        contra_flux<double>(c0e, Mrow, a.gamma - 1.0, y3);
 #pragma unroll
         for (int v = 0; v < 5; ++v) yg[v] = y3[0][v];
       }
-      {
-        const int f = g == 3 ? 0 : g + 1;
-        double N[3], cn[5], fb[5];
-        face_normal<double>(f, Md, N);
-        const double nn = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
-        const int nbf = f == 0 ? nbr[0] : f == 1 ? nbr[1] : f == 2 ? nbr[2] : nbr[3];
-        if (nbf >= 0) {
+      double N[3], fb[5];
+      face_normal<double>(fg, Me, N);
+      const double nn = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+      if (ng < 0) ghost_state<double>(-ng, c0e, N, far64, c0g);
+      num_flux<double>(a.flux, c0e, c0g, N, nn, a.gamma, fb);
 #pragma unroll
-          for (int v = 0; v < 5; ++v)
-            cn[v] = double(*reinterpret_cast<const S*>(ubase + (size_t)v * var_bytes + (uint32_t)nbf * sizeof(S)));
-        } else {
-          ghost_state<double>(-nbf, c0, N, far64, cn);
-        }
-        num_flux<double>(a.flux, c0, cn, N, nn, a.gamma, fb);
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-          x0[v] = g == 3 ? fb[v] : yg[v];
-          x1[v] = g == 3 ? 0.0 : fb[v];
-        }
-      }
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        const double a0 = a.mean_tab[(2 * mt) * 64 + lane], a1 = a.mean_tab[(2 * mt + 1) * 64 + lane];
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-          d4_t m = {0, 0, 0, 0};
-          m = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, x0[v], m, 0, 0, 0);
-          m = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, x1[v], m, 0, 0, 0);
-          mean_acc[mt][v] = m;
-        }
+      for (int v = 0; v < 5; ++v) {
+        x0[v] = g == 3 ? fb[v] : yg[v];
+        x1[v] = g == 3 ? 0.0 : fb[v];
       }
     }
     const double ivol = mv.inv_vol[e];
-    if (e < mv.n_elem) {
-      const char* u0base = reinterpret_cast<const char*>(a.u0);
-      char* obase = reinterpret_cast<char*>(a.u_out);
-      const bool comp = Pr::mixed && a.q_out != nullptr;
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        double o[5][4];
+    for (int mt = 0; mt < MT; ++mt) {
+      load_tile(mt);
+      double a0 = 0.0, a1 = 0.0;
+      if constexpr (Pr::mixed) {
+        a0 = a.mean_tab[(2 * mt) * 64 + lane];
+        a1 = a.mean_tab[(2 * mt + 1) * 64 + lane];
+      }
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        d4_t mean = {0, 0, 0, 0};
+        if constexpr (Pr::mixed) {
+          mean = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, x0[v], mean, 0, 0, 0);
+          mean = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, x1[v], mean, 0, 0, 0);
+        }
+        double o[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int mode = 16 * mt + drow_of<Pr>(g, j);
+          double r = double(acc[mt][v][j]);
+          if constexpr (Pr::mixed) r += mean[j];
+          r *= ivol;
+          const double out = a.rk ? a.alpha * u0v[v][j] + (1.0 - a.alpha) * (uin[v][j] + a.dt * r) : r;
+          o[j] = mode < NP ? out : 0.0;
+        }
+        if (!live) continue;
+        const size_t vo = (size_t)v * var_bytes + eoff;
+        if constexpr (!Pr::f64) {
+          const int qd = 4 * mt + g;
+          if (qd < NPQ) {
+            s4_t x;
 #pragma unroll
-          for (int v = 0; v < 5; ++v) {
-            double r = double(acc[mt][v][j]);
-            if constexpr (Pr::mixed) r += mean_acc[mt][v][j];
-            r *= ivol;
-            o[v][j] = 0.0;
-            if (mode < NP) {
-              const size_t off = (size_t)v * var_bytes + (size_t)mode * plane + eoff;
-              double out;
-              if (a.rk) {
-                const double uin = double(*reinterpret_cast<const S*>(ubase + off));
-                const double u0 = a.alpha == 0.0 ? 0.0 : double(*reinterpret_cast<const S*>(u0base + off));
-                out = a.alpha * u0 + (1.0 - a.alpha) * (uin + a.dt * r);
-              } else {
-                out = r;
-              }
-              *reinterpret_cast<S*>(obase + off) = S(out);
-              o[v][j] = out;
-            }
+            for (int j = 0; j < 4; ++j) x[j] = S(o[j]);
+            *reinterpret_cast<s4_t*>(obase + vo + (size_t)qd * quad_bytes) = x;
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int qd = 4 * mt + j;
+            if (qd < NPQ) *reinterpret_cast<S*>(obase + vo + (size_t)qd * quad_bytes + (size_t)g * sizeof(S)) = o[j];
           }
         }
         if constexpr (Pr::mixed) {
@@ -455,21 +552,20 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
             // operand companion of the result: modes 1.. in the operand precision, mean in fp32
             using E1 = typename Pr::E1;
             typedef E1 e4_t __attribute__((ext_vector_type(4)));
+            e4_t h;
 #pragma unroll
-            for (int v = 0; v < 5; ++v) {
-              e4_t h;
-#pragma unroll
-              for (int j = 0; j < 4; ++j) {
-                const int mode = 16 * mt + 4 * g + j;
-                h[j] = (E1)((mode > 0 && mode < NP) ? float(o[v][j]) : 0.0f);
-              }
-              *reinterpret_cast<e4_t*>(reinterpret_cast<E1*>(a.q_out) + ((int64_t)e * 5 + v) * (32 * KS) + 16 * mt +
-                                       4 * g) = h;
-              if (mt == 0 && g == 0) a.c0_out[v * epad + e] = float(o[v][0]);
+            for (int j = 0; j < 4; ++j) {
+              const int mode = 16 * mt + 4 * g + j;
+              h[j] = (E1)(mode > 0 ? float(o[j]) : 0.0f);
             }
+            *reinterpret_cast<e4_t*>(reinterpret_cast<E1*>(a.q_out) + ((int64_t)e * 5 + v) * (32 * KS) + 16 * mt +
+                                     4 * g) = h;
+            if (mt == 0 && g == 0) a.c0_out[v * epad + e] = float(o[0]);
           }
         }
       }
+    }
+    if (live) {
       if constexpr (Pr::mixed) {
         // zero the companion slots past the last mode tile
         if (comp) {
@@ -498,10 +594,10 @@ __global__ void pack_kernel(MeshView m, const double* __restrict__ u, typename P
   typename Pr::E1* dst = q + (e * 5 + v) * (32 * KS);
 #pragma unroll
   for (int mode = 0; mode < 32 * KS; ++mode) {
-    const float x = (mode > 0 && mode < NP) ? float(u[(int64_t)(v * NP + mode) * m.epad + e]) : 0.0f;
+    const float x = (mode > 0 && mode < NP) ? float(u[sidx(v, mode, e, m.epad, npq_of(NP))]) : 0.0f;
     dst[mode] = (typename Pr::E1)x;
   }
-  c0[v * m.epad + e] = float(u[(int64_t)(v * NP) * m.epad + e]);
+  c0[v * m.epad + e] = float(u[sidx(v, 0, e, m.epad, npq_of(NP))]);
 }
 
 size_t companion_bytes(int p, int64_t epad) {

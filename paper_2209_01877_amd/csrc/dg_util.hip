@@ -13,7 +13,8 @@ __global__ void set_state_kernel(MeshView m, int np, const double* __restrict__ 
   if (n >= m.epad) return;
   const int64_t src = m.perm[n];
   for (int v = 0; v < 5; ++v)
-    for (int i = 0; i < np; ++i) out[(int64_t)(v * np + i) * m.epad + n] = S(user[(src * 5 + v) * np + i]);
+    for (int i = 0; i < 4 * npq_of(np); ++i)
+      out[sidx(v, i, n, m.epad, npq_of(np))] = i < np ? S(user[(src * 5 + v) * np + i]) : S(0);
 }
 
 template <class S>
@@ -22,7 +23,7 @@ __global__ void get_state_kernel(MeshView m, int np, const S* __restrict__ in, d
   if (n >= m.n_elem) return;
   const int64_t dst = m.perm[n];
   for (int v = 0; v < 5; ++v)
-    for (int i = 0; i < np; ++i) user[(dst * 5 + v) * np + i] = double(in[(int64_t)(v * np + i) * m.epad + n]);
+    for (int i = 0; i < np; ++i) user[(dst * 5 + v) * np + i] = double(in[sidx(v, i, n, m.epad, npq_of(np))]);
 }
 
 __global__ void volume_points_kernel(MeshView m, int nq, RefView r, double* __restrict__ xyz) {
@@ -55,7 +56,10 @@ __global__ void project_kernel(MeshView m, int np, int nq, RefView r, double gam
     const double wb = 6.0 * r.qw[q] * r.B[q * np + i];
     for (int c = 0; c < 5; ++c) acc[c] += wb * U[c];
   }
-  for (int c = 0; c < 5; ++c) out[(int64_t)(c * np + i) * m.epad + n] = S(acc[c]);
+  for (int c = 0; c < 5; ++c) out[sidx(c, i, n, m.epad, npq_of(np))] = S(acc[c]);
+  if (i == 0)  // zero the padding modes of the last quad
+    for (int c = 0; c < 5; ++c)
+      for (int k = np; k < 4 * npq_of(np); ++k) out[sidx(c, k, n, m.epad, npq_of(np))] = S(0);
 }
 
 // Integrated slip-wall pressure J = sum_{wall faces} sum_q 2 A_f w^f_q p(U-_q) and dJ/dU,
@@ -70,7 +74,7 @@ __global__ void wall_pressure_kernel(MeshView m, int np, int nf, RefView r, doub
   const bool real = e < m.n_elem;
   if (grad)
     for (int v = 0; v < 5; ++v)
-      for (int i = 0; i < np; ++i) grad[(int64_t)(v * np + i) * m.epad + e] = S(0);
+      for (int i = 0; i < 4 * npq_of(np); ++i) grad[sidx(v, i, e, m.epad, npq_of(np))] = S(0);
   for (int f = 0; f < 4 && real; ++f) {
     if (m.nbr[f * m.epad + e] != -2) continue;
     double Mr[9];
@@ -83,7 +87,7 @@ __global__ void wall_pressure_kernel(MeshView m, int np, int nf, RefView r, doub
       const double* bq = r.Bf + ((int64_t)f * nf + q) * np;
       double U[5] = {0, 0, 0, 0, 0};
       for (int v = 0; v < 5; ++v)
-        for (int i = 0; i < np; ++i) U[v] += bq[i] * double(u[(int64_t)(v * np + i) * m.epad + e]);
+        for (int i = 0; i < np; ++i) U[v] += bq[i] * double(u[sidx(v, i, e, m.epad, npq_of(np))]);
       const double ir = 1.0 / U[0];
       const double vel[3] = {U[1] * ir, U[2] * ir, U[3] * ir};
       const double q2 = vel[0] * vel[0] + vel[1] * vel[1] + vel[2] * vel[2];
@@ -94,7 +98,7 @@ __global__ void wall_pressure_kernel(MeshView m, int np, int nf, RefView r, doub
         const double dp[5] = {gm1 * 0.5 * q2, -gm1 * vel[0], -gm1 * vel[1], -gm1 * vel[2], gm1};
         for (int v = 0; v < 5; ++v)
           for (int i = 0; i < np; ++i) {
-            S* gp = grad + (int64_t)(v * np + i) * m.epad + e;
+            S* gp = grad + sidx(v, i, e, m.epad, npq_of(np));
             *gp = S(double(*gp) + wq * dp[v] * bq[i]);
           }
       }
@@ -114,7 +118,7 @@ __global__ void local_dt_kernel(MeshView m, int np, double gamma, double scale, 
   if (e < m.n_elem) {
     double U[5];
     for (int v = 0; v < 5; ++v) {
-      const int64_t idx = (int64_t)(v * np) * m.epad + e;
+      const int64_t idx = sidx(v, 0, e, m.epad, npq_of(np));
       U[v] = f32 ? double(((const float*)u)[idx]) : ((const double*)u)[idx];
     }
     const double ir = 1.0 / U[0];

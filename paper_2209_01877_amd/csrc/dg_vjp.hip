@@ -143,8 +143,10 @@ __global__ __launch_bounds__(256) void vjp_kernel(VjpArgs a) {
   char* __restrict__ obase = reinterpret_cast<char*>(a.ubar);
   const MeshView& mv = a.mesh;
   const int64_t epad = mv.epad;
-  const uint32_t plane = (uint32_t)(epad * sizeof(S));
-  const uint32_t var_bytes = plane * NP;
+  constexpr int NPQ = npq_of(NP);
+  const uint32_t quad_bytes = (uint32_t)(epad * 4 * sizeof(S));
+  const uint32_t var_bytes = quad_bytes * NPQ;
+  auto moff = [&](int mode) { return (uint32_t)(mode >> 2) * quad_bytes + (uint32_t)(mode & 3) * sizeof(S); };
   const T gamma = T(a.gamma), gm1 = T(a.gamma - 1.0);
   T far[5];
 #pragma unroll
@@ -155,7 +157,7 @@ __global__ __launch_bounds__(256) void vjp_kernel(VjpArgs a) {
   for (int s = 0; s < KS; ++s) {
     const int mode = 4 * s + g;
     keep[s] = mode < NP;
-    off[s] = (uint32_t)(mode < NP ? mode : NP - 1) * plane;
+    off[s] = moff(mode < NP ? mode : NP - 1);
   }
 
   const int nblk = gridDim.x;
@@ -171,7 +173,7 @@ __global__ __launch_bounds__(256) void vjp_kernel(VjpArgs a) {
 
   for (int64_t grp = g_begin + wave_x; grp < g_end; grp += waves_x) {
     const int e = (int)(grp * 16 + col);
-    const uint32_t eoff = (uint32_t)e * sizeof(S);
+    const uint32_t eoff = (uint32_t)e * 4 * sizeof(S);
     double Md[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) Md[i] = mv.M[i * epad + e];
@@ -249,7 +251,7 @@ __global__ __launch_bounds__(256) void vjp_kernel(VjpArgs a) {
       const int nbf = mv.nbr[f * epad + e];
       const int fpl = (fcode >> (2 * f)) & 3;
       const int en = nbf >= 0 ? nbf : e;
-      const uint32_t enoff = (uint32_t)en * sizeof(S);
+      const uint32_t enoff = (uint32_t)en * 4 * sizeof(S);
       const T ivn = T(mv.inv_vol[en]);
       Op bn[5][KS], bwn[5][KS];
       load_ops<Pr, NP, KS>(ubase, var_bytes, enoff, off, keep, T(1), bn);
@@ -335,13 +337,17 @@ __global__ __launch_bounds__(256) void vjp_kernel(VjpArgs a) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int mode = 16 * mt + drow_of<Pr>(g, j);
-          if (mode < NP) {
+          // padding modes of the last quad are written 0
+          if ((mode >> 2) < npq_of(NP)) {
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
-              const size_t o = (size_t)v * var_bytes + (size_t)mode * plane + eoff;
-              double r = a.c * double(acc[mt][v][j]);
-              for (int k = 0; k < a.n_terms; ++k)
-                r += a.ya[k] * double(*reinterpret_cast<const S*>(reinterpret_cast<const char*>(a.y[k]) + o));
+              const size_t o = (size_t)v * var_bytes + moff(mode) + eoff;
+              double r = 0.0;
+              if (mode < NP) {
+                r = a.c * double(acc[mt][v][j]);
+                for (int k = 0; k < a.n_terms; ++k)
+                  r += a.ya[k] * double(*reinterpret_cast<const S*>(reinterpret_cast<const char*>(a.y[k]) + o));
+              }
               *reinterpret_cast<S*>(obase + o) = S(r);
             }
           }

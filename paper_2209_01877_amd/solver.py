@@ -27,8 +27,8 @@ class Solver:
     """One DG discretisation (order p, precision mode) of one tet mesh on one GPU.
 
     State tensors returned by this class are in the internal layout
-    [5][N_p][n_elem_pad] (renumbered element order); user-layout tensors are
-    [n_elem][5][N_p] float64 in the caller's element order.
+    [5][ceil(N_p/4)][n_elem_pad][4] (renumbered element order, four consecutive modes
+    innermost); user-layout tensors are [n_elem][5][N_p] float64 in the caller's order.
     """
 
     def __init__(self, p: int, precision: str = "fp64", gamma: float = 1.4, device: str = "cuda"):
@@ -103,8 +103,13 @@ class Solver:
         return dict(zip(keys, out.tolist()))
 
     # ----------------------------------------------------------------- state
+    @property
+    def state_shape(self):
+        """Internal layout [5][ceil(N_p/4)][n_elem_pad][4]."""
+        return (5, (self.n_modes + 3) // 4, self.n_elem_pad, 4)
+
     def new_state(self) -> torch.Tensor:
-        return torch.zeros((5, self.n_modes, self.n_elem_pad), dtype=self.state_dtype, device=self.device)
+        return torch.zeros(self.state_shape, dtype=self.state_dtype, device=self.device)
 
     def set_state(self, U_user: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
         assert U_user.dtype == torch.float64 and U_user.is_contiguous()
@@ -139,7 +144,7 @@ class Solver:
     # ----------------------------------------------------------------- hot path
     def _check_state(self, U: torch.Tensor) -> None:
         assert U.device.type == "cuda" and U.dtype == self.state_dtype and U.is_contiguous()
-        assert tuple(U.shape) == (5, self.n_modes, self.n_elem_pad)
+        assert tuple(U.shape) == self.state_shape
 
     def residual(self, U: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
         self._check_state(U)

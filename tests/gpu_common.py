@@ -53,3 +53,14 @@ def rel_err(dg, a, b) -> float:
     den = dg.l2_norm(b)
     den = torch.where(den > 0, den, torch.ones_like(den))
     return float((num / den).max())
+
+
+def zero_padding(s, X: torch.Tensor) -> torch.Tensor:
+    """Zero the padding of an internal-layout state [5][ceil(Np/4)][E_pad][4] in place:
+    elements past the mesh and the unused modes of the last mode quad."""
+    X[:, :, s.n_elem:] = 0
+    r = s.n_modes % 4
+    if r:
+        X[:, -1, :, r:] = 0
+    return X
+

@@ -13,7 +13,7 @@ from synthetic import fields, kuhn_cube
 
 pytestmark = pytest.mark.gpu
 
-from gpu_common import make_mesh, oracle, random_state, rel_err, solver  # noqa: E402
+from gpu_common import make_mesh, oracle, random_state, rel_err, solver, zero_padding  # noqa: E402
 
 FAR = (1.0, 0.5 * math.sqrt(1.4), 0.0, 0.0, 1.0)
 
@@ -86,8 +86,9 @@ def test_full_size_fifty_steps():
         if prec == "fp64":
             gen = torch.Generator(device="cuda").manual_seed(44)
             V = torch.randn(U0.shape, dtype=torch.float64, device="cuda", generator=gen)
-            V[:, 1:] *= 0.1
-            V[:, :, mesh.n_elem:] = 0
+            V *= 0.1
+            V[:, 0, :, 0] *= 10.0  # the cell means (mode 0) keep unit size
+            zero_padding(s, V)
             eps = 1e-6
 
             def J_of(U):
