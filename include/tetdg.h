@@ -125,8 +125,8 @@ int tdg_mesh_device_bytes(const tdg_ctx* ctx, size_t* bytes);
  * context computes.  Errors: TDG_ERR_STATE (no mesh), TDG_ERR_INVALID_ARG, TDG_ERR_HIP. */
 int tdg_mesh_bind(tdg_ctx* ctx, void* dev_buf, size_t bytes, void* hip_stream);
 
-/* Interface flux of eq. 11 (a tdg_flux value; default Rusanov).  The adjoint entry points
- * return TDG_ERR_UNSUPPORTED with the Roe flux. */
+/* Interface flux of eq. 11 (a tdg_flux value; default Rusanov).  The residual, the RK
+ * stages and the adjoint entry points all use the selected flux. */
 int tdg_set_flux(tdg_ctx* ctx, int flux);
 
 /* Free-stream primitive state (rho, u, v, w, p) used as the farfield ghost (host array). */

@@ -705,7 +705,6 @@ int tdg_residual_vjp_axpy(tdg_ctx* c, const void* U, const void* W, double cw, i
   int st = require_bound(c);
   if (st) return st;
   if (!U || !W || !Out || Out == U || Out == W) return fail(c, TDG_ERR_INVALID_ARG, "U, W, Out must be distinct");
-  if (c->flux != TDG_FLUX_RUSANOV) return fail(c, TDG_ERR_UNSUPPORTED, "the adjoint is implemented for the Rusanov flux");
   if (n_terms < 0 || n_terms > 3 || (n_terms > 0 && (!Y || !ya))) return fail(c, TDG_ERR_INVALID_ARG, "bad terms");
   VjpArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -722,6 +721,7 @@ int tdg_residual_vjp_axpy(tdg_ctx* c, const void* U, const void* W, double cw, i
   a.mesh = view(c);
   a.tab = c->dev + c->off_vtab;
   a.gamma = c->gamma;
+  a.flux = c->flux;
   for (int v = 0; v < 5; ++v) a.far[v] = c->far[v];
   hipError_t e = launch_vjp(c->p, c->prec, a, (hipStream_t)s);
   return e == hipSuccess ? TDG_OK : hip_fail(c, e, "vjp launch");
@@ -731,7 +731,6 @@ int tdg_residual_vjp(tdg_ctx* c, const void* U, const void* W, void* Ubar, void*
   int st = require_bound(c);
   if (st) return st;
   if (!U || !W || !Ubar || Ubar == U || Ubar == W) return fail(c, TDG_ERR_INVALID_ARG, "U, W, Ubar must be distinct");
-  if (c->flux != TDG_FLUX_RUSANOV) return fail(c, TDG_ERR_UNSUPPORTED, "the adjoint is implemented for the Rusanov flux");
   VjpArgs a;
   std::memset(&a, 0, sizeof(a));
   a.c = 1.0;
@@ -741,6 +740,7 @@ int tdg_residual_vjp(tdg_ctx* c, const void* U, const void* W, void* Ubar, void*
   a.mesh = view(c);
   a.tab = c->dev + c->off_vtab;
   a.gamma = c->gamma;
+  a.flux = c->flux;
   for (int v = 0; v < 5; ++v) a.far[v] = c->far[v];
   hipError_t e = launch_vjp(c->p, c->prec, a, (hipStream_t)s);
   if (e == hipErrorNotSupported) return fail(c, TDG_ERR_UNSUPPORTED, "VJP not available for this mode");

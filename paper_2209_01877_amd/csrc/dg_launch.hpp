@@ -42,6 +42,7 @@ struct VjpArgs {
   const void* tab;    // packed VJP operand tables (f64 or f32)
   double gamma;
   double far[5];
+  int flux;           // numerical flux: 0 Rusanov, 1 Roe
 };
 
 struct RefView {

@@ -14,6 +14,8 @@
 //           Ubar    += B_f^T Ubar-_q
 // Every element gathers its neighbours' U and W and writes only its own Ubar: no
 // atomics.  Ties of max(lambda-, lambda+) split the derivative evenly; d|x| = 0 at 0.
+// Rusanov's and Roe's fluxes are both antisymmetric under exchanging the states and
+// negating the normal, which the interior-face rule above relies on.
 #include <hip/hip_runtime.h>
 
 #include "dg_kernels.hpp"
@@ -111,6 +113,158 @@ __device__ __forceinline__ void rusanov_vjp(const T a[5], const T b[5], const T 
   }
 }
 
+// (dFhat/da)^T g and (dFhat/db)^T g for the Roe flux Fhat_N(a, b) (the forward
+// evaluation in roe_n, differentiated in reverse order).  The central part reuses
+// flux_n_vjp; the dissipation -|N|/2 sum_k |lambda_k| alpha_k r_k is taken through the
+// Roe averages back to both states.  Harten's fix is C1 at |lambda| = delta, and d|x| = 0
+// at x = 0 for the entropy/shear waves.
+template <class T>
+__device__ __forceinline__ void roe_vjp(const T a[5], const T b[5], const T N[3], T nn, T gamma, const T g[5], T ga[5],
+                                        T gb[5], bool need_b) {
+  const T gm1 = gamma - T(1), hf = T(0.5);
+  const T inn = T(1) / nn;
+  const T n[3] = {N[0] * inn, N[1] * inn, N[2] * inn};
+  // ---- forward
+  const T rl = a[0], rr = b[0];
+  const T irl = T(1) / rl, irr = T(1) / rr;
+  const T ul[3] = {a[1] * irl, a[2] * irl, a[3] * irl};
+  const T ur[3] = {b[1] * irr, b[2] * irr, b[3] * irr};
+  const T kl = ul[0] * ul[0] + ul[1] * ul[1] + ul[2] * ul[2];
+  const T kr = ur[0] * ur[0] + ur[1] * ur[1] + ur[2] * ur[2];
+  const T pl = gm1 * (a[4] - hf * rl * kl), pr = gm1 * (b[4] - hf * rr * kr);
+  const T hl = (a[4] + pl) * irl, hr = (b[4] + pr) * irr;
+  const T sl = sqrt(rl), sr = sqrt(rr);
+  const T iw = T(1) / (sl + sr);
+  const T rho = sl * sr;
+  T u[3], du[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    u[d] = (sl * ul[d] + sr * ur[d]) * iw;
+    du[d] = ur[d] - ul[d];
+  }
+  const T h = (sl * hl + sr * hr) * iw;
+  const T q2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  const T c = sqrt(gm1 * (h - hf * q2));
+  const T ic2 = T(1) / (c * c);
+  const T un = u[0] * n[0] + u[1] * n[1] + u[2] * n[2];
+  const T dr = rr - rl, dp = pr - pl;
+  const T dun = du[0] * n[0] + du[1] * n[1] + du[2] * n[2];
+  const T del = T(0.1) * c;
+  const T lm1 = un - c, lm4 = un + c;
+  const bool f1 = fabs(lm1) < del, f4 = fabs(lm4) < del;
+  const T l1 = f1 ? (lm1 * lm1 + del * del) * hf / del : fabs(lm1);
+  const T l4 = f4 ? (lm4 * lm4 + del * del) * hf / del : fabs(lm4);
+  const T l2 = fabs(un);
+  const T s = hf * ic2;
+  const T a1 = (dp - rho * c * dun) * s;
+  const T a2 = dr - dp * ic2;
+  const T a4 = (dp + rho * c * dun) * s;
+  const T k1 = l1 * a1, k2 = l2 * a2, k3 = l2 * rho, k4 = l4 * a4;
+  const T udu = u[0] * du[0] + u[1] * du[1] + u[2] * du[2];
+  // ---- reverse: the dissipation enters the flux as -|N|/2 diss
+  T G[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) G[v] = -hf * nn * g[v];
+  const T Gn = G[1] * n[0] + G[2] * n[1] + G[3] * n[2];
+  T gu[3], gdu[3];
+  T gk1 = G[0] + G[4] * (h - un * c), gk2 = G[0] + G[4] * hf * q2;
+  T gk3 = G[4] * (udu - un * dun), gk4 = G[0] + G[4] * (h + un * c);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    gk1 += G[1 + d] * (u[d] - c * n[d]);
+    gk2 += G[1 + d] * u[d];
+    gk3 += G[1 + d] * (du[d] - dun * n[d]);
+    gk4 += G[1 + d] * (u[d] + c * n[d]);
+    gu[d] = G[1 + d] * (k1 + k2 + k4) + G[4] * k3 * du[d];
+    gdu[d] = G[1 + d] * k3 + G[4] * k3 * u[d];
+  }
+  T gc = (k4 - k1) * Gn + G[4] * un * (k4 - k1);
+  T gdun = -k3 * Gn - G[4] * k3 * un;
+  T gun = G[4] * c * (k4 - k1) - G[4] * k3 * dun;
+  T gh = G[4] * (k1 + k4);
+  T gq2 = G[4] * hf * k2;
+  const T gl1 = gk1 * a1, gl2 = gk2 * a2 + gk3 * rho, gl4 = gk4 * a4;
+  const T ga1 = gk1 * l1, ga2 = gk2 * l2, ga4 = gk4 * l4;
+  T grho = gk3 * l2;
+  // alpha_k
+  T gdp = (ga1 + ga4) * s - ga2 * ic2;
+  const T gdr = ga2;
+  grho += (ga4 - ga1) * c * dun * s;
+  gc += (ga4 - ga1) * rho * dun * s;
+  gdun += (ga4 - ga1) * rho * c * s;
+  const T gic2 = hf * (ga1 * (dp - rho * c * dun) + ga4 * (dp + rho * c * dun)) - ga2 * dp;
+  // wave speeds (Harten: fix = (lam^2 + del^2) / (2 del), del = 0.1 c)
+  {
+    const T sg2 = un > T(0) ? T(1) : (un < T(0) ? T(-1) : T(0));
+    gun += gl2 * sg2;
+    const T d1 = f1 ? lm1 / del : (lm1 > T(0) ? T(1) : (lm1 < T(0) ? T(-1) : T(0)));
+    const T d4 = f4 ? lm4 / del : (lm4 > T(0) ? T(1) : (lm4 < T(0) ? T(-1) : T(0)));
+    gun += gl1 * d1 + gl4 * d4;
+    gc += -gl1 * d1 + gl4 * d4;
+    if (f1) gc += gl1 * (del * del - lm1 * lm1) * hf / (del * del) * T(0.1);
+    if (f4) gc += gl4 * (del * del - lm4 * lm4) * hf / (del * del) * T(0.1);
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    gu[d] += gun * n[d];
+    gdu[d] += gdun * n[d];
+  }
+  gc += gic2 * (-T(2) * ic2 / c);
+  // c = sqrt(gm1 (h - q2 / 2))
+  gh += gc * gm1 * hf / c;
+  gq2 += -gc * gm1 * T(0.25) / c;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) gu[d] += T(2) * u[d] * gq2;
+  // Roe averages
+  T gsl = gh * hl * iw + grho * sr, gsr = gh * hr * iw + grho * sl;
+  const T ghl = gh * sl * iw, ghr = gh * sr * iw;
+  T giw = gh * (sl * hl + sr * hr);
+  T gul[3], gur[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    gsl += iw * gu[d] * ul[d];
+    gsr += iw * gu[d] * ur[d];
+    gul[d] = gu[d] * sl * iw - gdu[d];
+    gur[d] = gu[d] * sr * iw + gdu[d];
+    giw += gu[d] * (sl * ul[d] + sr * ur[d]);
+  }
+  gsl += -giw * iw * iw;
+  gsr += -giw * iw * iw;
+  T grl = gsl * hf / sl - gdr, grr = gsr * hf / sr + gdr;
+  T gpl = -gdp + ghl * irl, gpr = gdp + ghr * irr;
+  T gal4 = ghl * irl, gbr4 = ghr * irr;
+  T girl = ghl * (a[4] + pl), girr = ghr * (b[4] + pr);
+  // pressures
+  gal4 += gpl * gm1;
+  gbr4 += gpr * gm1;
+  grl += -gpl * gm1 * hf * kl;
+  grr += -gpr * gm1 * hf * kr;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    gul[d] += -gpl * gm1 * rl * ul[d];
+    gur[d] += -gpr * gm1 * rr * ur[d];
+    girl += gul[d] * a[1 + d];
+    girr += gur[d] * b[1 + d];
+  }
+  grl += -girl * irl * irl;
+  grr += -girr * irr * irr;
+  // central part (F(a).N + F(b).N) / 2
+  T fa[5];
+  flux_n_vjp<T>(a, N, g, gm1, fa);
+  ga[0] = hf * fa[0] + grl;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) ga[1 + d] = hf * fa[1 + d] + gul[d] * irl;
+  ga[4] = hf * fa[4] + gal4;
+  if (need_b) {
+    T fb[5];
+    flux_n_vjp<T>(b, N, g, gm1, fb);
+    gb[0] = hf * fb[0] + grr;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) gb[1 + d] = hf * fb[1 + d] + gur[d] * irr;
+    gb[4] = hf * fb[4] + gbr4;
+  }
+}
+
 template <class Pr, int NP, int KS>
 __device__ __forceinline__ void load_ops(const char* __restrict__ base, uint32_t var_bytes, uint32_t elem_off,
                                          const uint32_t (&off)[KS], const bool (&keep)[KS], typename Pr::T scale,
@@ -125,7 +279,8 @@ __device__ __forceinline__ void load_ops(const char* __restrict__ base, uint32_t
     }
 }
 
-template <int P, class Pr>
+// kRoe selects the face flux at compile time (Roe's adjoint needs more registers).
+template <int P, class Pr, bool kRoe>
 __global__ __launch_bounds__(256) void vjp_kernel(VjpArgs a) {
   using O = Ord<P>;
   using V = VjpLayout<P>;
@@ -302,7 +457,10 @@ __global__ __launch_bounds__(256) void vjp_kernel(VjpArgs a) {
 #pragma unroll
           for (int v = 0; v < 5; ++v) gcot[v] = bnd ? -T(wm[v][j]) : T(wp[v][j]) - T(wm[v][j]);
           if (q < NF) {
-            rusanov_vjp<T>(um, up, N, nn, gamma, gcot, ga, gb, bnd);
+            if constexpr (kRoe)
+              roe_vjp<T>(um, up, N, nn, gamma, gcot, ga, gb, bnd);
+            else
+              rusanov_vjp<T>(um, up, N, nn, gamma, gcot, ga, gb, bnd);
             if (bnd) {
               if (-nbf == 2) {  // slip wall: ghost = (rho, m - 2 (m.n) n, E), symmetric Jacobian
                 const T nn2 = N[0] * N[0] + N[1] * N[1] + N[2] * N[2];
@@ -358,7 +516,7 @@ __global__ __launch_bounds__(256) void vjp_kernel(VjpArgs a) {
 
 template <int P, class Pr>
 hipError_t launch_vjp_impl(const VjpArgs& a, hipStream_t stream) {
-  auto kern = vjp_kernel<P, Pr>;
+  auto kern = a.flux == 1 ? vjp_kernel<P, Pr, true> : vjp_kernel<P, Pr, false>;
   int per_cu = 0;
   hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0);
   if (err != hipSuccess) return err;

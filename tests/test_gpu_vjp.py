@@ -9,6 +9,7 @@ import torch
 
 from oracle.adjoint import residual_vjp as oracle_vjp
 from oracle.adjoint import trajectory_vjp as oracle_traj
+from oracle.dg import DG
 from synthetic import fields, kuhn_cube
 
 pytestmark = pytest.mark.gpu
@@ -51,6 +52,57 @@ def test_vjp_boundaries(p):
     got = gpu_vjp(solver(p, "fp64", mesh, farfield=far), U, W)
     err = rel_err(dg, got, ref)
     print(f"p={p} boundary vjp rel L2 error {err:.3e}")
+    assert err < 1e-12
+
+
+def sonic_state(n_elem, n_modes, seed):
+    """Cell means of a Mach-1 flow along x (rho ~ 1, u_x in [1.0, 1.35] around c = 1.18,
+    p = 1): on the mesh's x-normal faces u.n -+ c falls inside Harten's entropy-fix band
+    |lambda| < 0.1 c, so both branches of the Roe wave speeds are exercised."""
+    U = fields.random_coefficients(n_elem, n_modes, seed=seed, scale=0.01)
+    rng = np.random.default_rng(seed + 1)
+    rho = rng.uniform(0.95, 1.05, n_elem)
+    u = np.stack([rng.uniform(1.0, 1.35, n_elem), rng.uniform(-0.1, 0.1, n_elem), rng.uniform(-0.1, 0.1, n_elem)], 1)
+    U[:, 0, 0] = rho
+    U[:, 1:4, 0] = rho[:, None] * u
+    U[:, 4, 0] = 1.0 / 0.4 + 0.5 * rho * (u * u).sum(1)
+    return torch.from_numpy(U)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("state", ["subsonic", "sonic"])
+def test_roe_vjp_vs_oracle(p, prec, state):
+    """Adjoint of the residual with Roe's flux against the oracle's reverse mode."""
+    mesh = make_mesh("ragged")
+    dg = DG(p, mesh.elem_vid, mesh.elem_xyz, mesh.bface_vid, mesh.bface_tag, flux="roe")
+    U = random_state(dg, seed=5) if state == "subsonic" else sonic_state(dg.n_elem, dg.Np, 9)
+    if state == "sonic":
+        ux = (U[:, 1, 0] / U[:, 0, 0]).numpy()
+        c = np.sqrt(1.4 * 0.4 * (U[:, 4, 0] - 0.5 * (U[:, 1:4, 0] ** 2).sum(1) / U[:, 0, 0]).numpy() / U[:, 0, 0].numpy())
+        assert (np.abs(ux - c) < 0.1 * c).mean() > 0.2  # the entropy-fix band is populated
+    W = torch.from_numpy(fields.gaussian(U.shape, 43))
+    ref = oracle_vjp(dg, U, W)
+    s = solver(p, prec, mesh)
+    s.set_flux("roe")
+    got = gpu_vjp(s, U, W)
+    err = rel_err(dg, got, ref)
+    print(f"roe p={p} {prec} {state} vjp rel L2 error {err:.3e}")
+    assert err < TOL[prec]
+
+
+def test_roe_vjp_boundaries():
+    far = (1.0, 0.5 * math.sqrt(1.4), 0.0, 0.0, 1.0)
+    mesh = make_mesh("bump")
+    dg = DG(2, mesh.elem_vid, mesh.elem_xyz, mesh.bface_vid, mesh.bface_tag, farfield_prim=far, flux="roe")
+    U = random_state(dg, seed=8)
+    W = torch.from_numpy(fields.gaussian(U.shape, 43))
+    ref = oracle_vjp(dg, U, W)
+    s = solver(2, "fp64", mesh, farfield=far)
+    s.set_flux("roe")
+    got = gpu_vjp(s, U, W)
+    err = rel_err(dg, got, ref)
+    print(f"roe boundary vjp rel L2 error {err:.3e}")
     assert err < 1e-12
 
 
