@@ -107,6 +107,10 @@ def run_gpu(args):
         # operand companion of U once per call; each stage writes the next one's)
         s.rk_step(U, dt, args.warmup, work)
         t = timed(lambda: s.rk_step(U, dt, args.steps, work), 1, 0)
+        # dual-phase timing (difference of two run lengths, as in the paper's measurement):
+        # removes the per-call fixed cost (companion build, launch of the first stage)
+        t_short = timed(lambda: s.rk_step(U, dt, 10, work), 1, 0)
+        t_long = timed(lambda: s.rk_step(U, dt, 10 + args.steps, work), 1, 0)
         s.sync()
         dof = mesh.n_elem * s.n_modes * 5
         stages = 3 * args.steps
@@ -122,6 +126,7 @@ def run_gpu(args):
         results[prec] = {
             "gdof_per_s_per_stage": gdofs,
             "ms_per_step": 1e3 * t / args.steps,
+            "dual_phase_gdof_per_s_per_stage": dof * stages / (t_long - t_short) / 1e9,
             "residual_gdof_per_s": dof * args.steps / tr / 1e9,
             "residual_ms": 1e3 * tr / args.steps,
             "stage_hbm_gb_per_s": stage_bytes(mesh.n_elem, s.n_modes, sb) * args.steps / t / 1e9,
@@ -234,7 +239,7 @@ def main():
     ap.add_argument("--p", type=int, default=3)
     ap.add_argument("--renumber", default="hilbert")
     ap.add_argument("--precisions", default="bf16,fp32,fp16,fp64")
-    ap.add_argument("--cpu-n", type=int, default=16)
+    ap.add_argument("--cpu-n", type=int, default=28)
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the P4 and adjoint workloads")

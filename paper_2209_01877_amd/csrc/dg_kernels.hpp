@@ -192,10 +192,10 @@ __device__ __forceinline__ void roe_n(const T um[5], const T up[5], const T N[3]
   out[4] = hh * ((um[4] + pl) * unl + (up[4] + pr) * unr) - hh * nn * diss[4];
 }
 
-// Numerical flux selected at run time: 0 Rusanov, 1 Roe.
-template <class T>
-__device__ __forceinline__ void num_flux(int kind, const T um[5], const T up[5], const T N[3], T nn, T gamma, T out[5]) {
-  if (kind == 1)
+// Numerical flux chosen at compile time (Roe when kRoe, else Rusanov).
+template <bool kRoe, class T>
+__device__ __forceinline__ void num_flux(const T um[5], const T up[5], const T N[3], T nn, T gamma, T out[5]) {
+  if constexpr (kRoe)
     roe_n<T>(um, up, N, nn, gamma, out);
   else
     rusanov_n<T>(um, up, N, nn, gamma, out);

@@ -105,7 +105,9 @@ constexpr int stage_min_blocks() {
   return (P <= 3 && !Pr::f64) ? 2 : 1;
 }
 
-template <int P, class Pr, bool kLds>
+// kLds: reference tables staged in LDS; kRoe: Roe's interface flux instead of Rusanov's
+// (a compile-time choice keeps the other flux's code and registers out of the kernel).
+template <int P, class Pr, bool kLds, bool kRoe>
 __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel(StageArgs a) {
   using O = Ord<P>;
   using L = Layout<P, Pr::KW>;
@@ -303,7 +305,7 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
       T fhbar[5];
       if constexpr (Pr::mixed) {
         if (nbf < 0) ghost_state<T>(-nbf, c0t, N, far, c0n);
-        num_flux<T>(a.flux, c0t, c0n, N, nn, gamma, fhbar);
+        num_flux<kRoe, T>(c0t, c0n, N, nn, gamma, fhbar);
       }
 #pragma unroll 1
       for (int ft = 0; ft < FT; ++ft) {
@@ -362,7 +364,7 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
           }
           if (nbf < 0) ghost_state<T>(-nbf, um, N, far, up);
           if (q < NF) {
-            num_flux<T>(a.flux, um, up, N, nn, gamma, fl);
+            num_flux<kRoe, T>(um, up, N, nn, gamma, fl);
           } else {
 #pragma unroll
             for (int v = 0; v < 5; ++v) fl[v] = Pr::mixed ? fhbar[v] : T(0);
@@ -497,7 +499,7 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
       face_normal<double>(fg, Me, N);
       const double nn = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
       if (ng < 0) ghost_state<double>(-ng, c0e, N, far64, c0g);
-      num_flux<double>(a.flux, c0e, c0g, N, nn, a.gamma, fb);
+      num_flux<kRoe, double>(c0e, c0g, N, nn, a.gamma, fb);
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         x0[v] = g == 3 ? fb[v] : yg[v];
@@ -629,7 +631,7 @@ static hipError_t launch_stage_impl(const StageArgs& a, hipStream_t stream) {
   using L = Layout<P, Pr::KW>;
   constexpr size_t tab_bytes = sizeof(typename Pr::Op) * L::n_slots * 64;
   constexpr bool lds = tab_bytes <= 96 * 1024;
-  auto kern = stage_kernel<P, Pr, lds>;
+  auto kern = a.flux == 1 ? stage_kernel<P, Pr, lds, true> : stage_kernel<P, Pr, lds, false>;
   int per_cu = 0;
   hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0);
   if (err != hipSuccess) return err;
