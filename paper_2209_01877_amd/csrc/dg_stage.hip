@@ -118,6 +118,9 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
   constexpr int NP = O::NP, NQ = O::NQ, NF = O::NF, MT = O::MT, QT = O::QT, FT = O::FT, KS = L::KS;
 
   __shared__ Op lds_tab[kLds ? L::n_slots * 64 : 1];
+  // mixed modes: per-wave staging of the operand companion written by the epilogue, so
+  // that each element's record leaves as whole 16-byte slots (16 elements x 5 x KS x 4)
+  __shared__ Op lds_comp[Pr::mixed ? 4 * 16 * 5 * KS * 4 : 1];
   const Op* __restrict__ tab;
   if constexpr (kLds) {
     const Op* src = reinterpret_cast<const Op*>(a.tab);
@@ -129,6 +132,7 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
   }
 
   const int lane = threadIdx.x & 63, g = lane >> 4, col = lane & 15;
+  const int wslot = threadIdx.x >> 6;  // wavefront within the workgroup
   const char* __restrict__ ubase = reinterpret_cast<const char*>(a.u_in);
   const MeshView& mv = a.mesh;
   const int64_t epad = mv.epad;
@@ -560,23 +564,33 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
               const int mode = 16 * mt + 4 * g + j;
               h[j] = (E1)(mode > 0 ? float(o[j]) : 0.0f);
             }
-            *reinterpret_cast<e4_t*>(reinterpret_cast<E1*>(a.q_out) + ((int64_t)e * 5 + v) * (32 * KS) + 16 * mt +
-                                     4 * g) = h;
+            // modes 16 mt + 4 g .. + 3 of (col, v) into this wave's staging record
+            *reinterpret_cast<e4_t*>(reinterpret_cast<E1*>(lds_comp) + ((wslot * 16 + col) * 5 + v) * (32 * KS) +
+                                     16 * mt + 4 * g) = h;
             if (mt == 0 && g == 0) a.c0_out[v * epad + e] = float(o[0]);
           }
         }
       }
     }
-    if (live) {
-      if constexpr (Pr::mixed) {
-        // zero the companion slots past the last mode tile
-        if (comp) {
+    if constexpr (Pr::mixed) {
+      if (comp) {
+        // slots past the last mode tile are zero; then every lane sends the 16-byte slot it
+        // reads as an MFMA operand (modes 32 s + 8 g .. + 7), so the 4 lanes of a column
+        // write their element's whole record
+        using E1 = typename Pr::E1;
 #pragma unroll
-          for (int mt = MT; mt < 2 * KS; ++mt)
+        for (int mt = MT; mt < 2 * KS; ++mt)
 #pragma unroll
-            for (int v = 0; v < 5; ++v)
-              *reinterpret_cast<uint2*>(reinterpret_cast<typename Pr::E1*>(a.q_out) + ((int64_t)e * 5 + v) * (32 * KS) +
-                                        16 * mt + 4 * g) = uint2{0, 0};
+          for (int v = 0; v < 5; ++v)
+            *reinterpret_cast<uint2*>(reinterpret_cast<E1*>(lds_comp) + ((wslot * 16 + col) * 5 + v) * (32 * KS) +
+                                      16 * mt + 4 * g) = uint2{0, 0};
+        if (live) {
+#pragma unroll
+          for (int v = 0; v < 5; ++v)
+#pragma unroll
+            for (int s = 0; s < KS; ++s)
+              reinterpret_cast<Op*>(a.q_out)[(((int64_t)e * 5 + v) * KS + s) * 4 + g] =
+                  lds_comp[(((wslot * 16 + col) * 5 + v) * KS + s) * 4 + g];
         }
       }
     }
