@@ -177,6 +177,16 @@ int tdg_residual(tdg_ctx* ctx, const void* U, void* R, void* hip_stream);
  * stage (mixed modes: plus one companion pass over U per call). */
 int tdg_rk_step(tdg_ctx* ctx, void* U, void* work, double dt, int n_steps, void* hip_stream);
 
+/* n_steps SSP-RK3 steps with the step size chosen on the device before every step
+ * (Sec. III.C: the global minimum of the local time steps):
+ *   dt_k = min_K cfl d_K / ((2p+1)(|u_K| + c_K)),  d_K = 6|K| / sum_f A_f,
+ * with the cell means of the current U (as tdg_stable_dt), then one step as tdg_rk_step.
+ * dt_k is written to dt_hist[k] (device, n_steps doubles) and read there by the stage
+ * kernels, so the loop needs no host round trip.  U, work: as tdg_rk_step.
+ * Errors: TDG_ERR_INVALID_ARG (null pointers, cfl <= 0, n_steps < 0). */
+int tdg_rk_step_adaptive(tdg_ctx* ctx, void* U, void* work, double cfl, int n_steps, double* dt_hist,
+                         void* hip_stream);
+
 /* Bytes of the work buffer tdg_rk_step needs. */
 int tdg_work_bytes(const tdg_ctx* ctx, size_t* bytes);
 

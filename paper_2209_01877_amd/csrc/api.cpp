@@ -679,6 +679,52 @@ int tdg_rk_step(tdg_ctx* c, void* U, void* work, double dt, int n_steps, void* s
   return TDG_OK;
 }
 
+int tdg_rk_step_adaptive(tdg_ctx* c, void* U, void* work, double cfl, int n_steps, double* dt_hist, void* s) {
+  int st = require_bound(c);
+  if (st) return st;
+  if (!U || !work || !dt_hist) return fail(c, TDG_ERR_INVALID_ARG, "null state, work or dt pointer");
+  if (n_steps < 0 || !(cfl > 0.0) || !std::isfinite(cfl)) return fail(c, TDG_ERR_INVALID_ARG, "bad cfl or n_steps");
+  char* w = (char*)work;
+  void* U1 = w;
+  void* U2 = w + state_bytes(c);
+  void* q[3] = {nullptr, nullptr, nullptr};
+  float* c0[3] = {nullptr, nullptr, nullptr};
+  if (is_mixed(c)) {
+    for (int k = 0; k < 3; ++k) comp_ptrs(c, w + 2 * state_bytes(c) + k * comp_bytes(c), &q[k], &c0[k]);
+    if (n_steps > 0) {
+      hipError_t e = launch_pack(c->p, c->prec, view(c), U, q[0], c0[0], (hipStream_t)s);
+      if (e != hipSuccess) return hip_fail(c, e, "pack launch");
+    }
+  }
+  StageArgs a = stage_args(c);
+  a.rk = 1;
+  a.dt = 0.0;
+  for (int k = 0; k < n_steps; ++k) {
+    // dt_k = min over elements of the local stable step of the current U, on the device
+    hipError_t e = launch_local_dt(c->p, c->prec, view(c), c->gamma, cfl, U, dt_hist + k, (hipStream_t)s);
+    if (e != hipSuccess) return hip_fail(c, e, "stable dt launch");
+    a.dt_dev = dt_hist + k;
+    const void* ins[3] = {U, U1, U2};
+    const void* base[3] = {nullptr, U, U};
+    void* outs[3] = {U1, U2, U};
+    const double alphas[3] = {0.0, 0.75, 1.0 / 3.0};
+    const int qin[3] = {0, 1, 2}, qout[3] = {1, 2, 0};
+    for (int stg = 0; stg < 3; ++stg) {
+      a.u_in = ins[stg];
+      a.u0 = base[stg];
+      a.u_out = outs[stg];
+      a.alpha = alphas[stg];
+      a.q_in = q[qin[stg]];
+      a.c0_in = c0[qin[stg]];
+      a.q_out = q[qout[stg]];
+      a.c0_out = c0[qout[stg]];
+      e = launch_stage(c->p, c->prec, a, (hipStream_t)s);
+      if (e != hipSuccess) return hip_fail(c, e, "rk stage launch");
+    }
+  }
+  return TDG_OK;
+}
+
 int tdg_rk_stage(tdg_ctx* c, const void* U_in, const void* U0, void* U_out, double alpha, double dt, void* s) {
   int st = require_bound(c);
   if (st) return st;

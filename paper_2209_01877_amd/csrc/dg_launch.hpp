@@ -11,6 +11,7 @@ struct StageArgs {
   const void* u0;     // RK stage base state (may be null when alpha == 0)
   void* u_out;        // residual or stage result
   double alpha, dt;   // U_out = alpha U0 + (1 - alpha)(U_in + dt R)
+  const double* dt_dev;  // when non-null, dt is read from this device scalar instead
   int rk;             // 0: store R, 1: store the stage update
   int max_blocks;     // 0: fill the device once
   MeshView mesh;

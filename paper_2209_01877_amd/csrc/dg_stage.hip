@@ -140,6 +140,7 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
   const uint32_t quad_bytes = (uint32_t)(epad * 4 * sizeof(S));  // one (variable, mode quad) plane
   const uint32_t var_bytes = quad_bytes * NPQ;
   const T gamma = T(a.gamma), gm1 = T(a.gamma - 1.0);
+  const double dt = a.dt_dev ? *a.dt_dev : a.dt;  // step size (device-computed when adaptive)
   T far[5];
   double far64[5];
 #pragma unroll
@@ -533,7 +534,7 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
           double r = double(acc[mt][v][j]);
           if constexpr (Pr::mixed) r += mean[j];
           r *= ivol;
-          const double out = a.rk ? a.alpha * u0v[v][j] + (1.0 - a.alpha) * (uin[v][j] + a.dt * r) : r;
+          const double out = a.rk ? a.alpha * u0v[v][j] + (1.0 - a.alpha) * (uin[v][j] + dt * r) : r;
           o[j] = mode < NP ? out : 0.0;
         }
         if (!live) continue;

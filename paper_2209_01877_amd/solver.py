@@ -170,6 +170,21 @@ class Solver:
               self._ctx, "tdg_rk_step")
         return U
 
+    def rk_step_adaptive(self, U: torch.Tensor, cfl: float, n_steps: int = 1, work: torch.Tensor | None = None,
+                         stream=None) -> torch.Tensor:
+        """n SSP-RK3 steps in place on U, each with dt = the device minimum of the local stable
+        steps of the current U (no host synchronisation).  Returns the steps taken, a device
+        tensor of n_steps doubles."""
+        self._check_state(U)
+        work = self.new_work() if work is None else work
+        size = ctypes.c_size_t()
+        check(lib.tdg_work_bytes(self._ctx, ctypes.byref(size)), self._ctx)
+        assert work.is_cuda and work.numel() * work.element_size() >= size.value
+        dts = torch.empty(max(1, int(n_steps)), dtype=torch.float64, device=self.device)
+        check(lib.tdg_rk_step_adaptive(self._ctx, _ptr(U), _ptr(work), float(cfl), int(n_steps), _ptr(dts),
+                                       _stream(stream)), self._ctx, "tdg_rk_step_adaptive")
+        return dts[:n_steps]
+
     def residual_vjp(self, U: torch.Tensor, W: torch.Tensor, out: torch.Tensor | None = None,
                      stream=None) -> torch.Tensor:
         self._check_state(U)

@@ -149,6 +149,38 @@ def test_stable_dt(prec):
     assert abs(dt - ref) < (1e-14 if prec != "fp32" else 1e-6) * ref
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_rk_step_adaptive(prec):
+    """Steps sized on the device every step (minimum of the local stable steps of the current
+    state): bitwise equal to fixed-step calls with the same step sizes, and against the
+    oracle taking the same rule on the host (step sizes and end state)."""
+    mesh = make_mesh("jitter4")
+    dg = oracle(2, mesh)
+    U = torch.from_numpy(fields.random_coefficients(dg.n_elem, dg.Np, seed=21, scale=0.01))
+    n, cfl = 6, 0.3
+    ref, dts_ref = U.clone(), []
+    for _ in range(n):
+        dts_ref.append(dg.local_dt_min(ref, cfl=cfl))
+        ref = dg.rk3_step(ref, dts_ref[-1])
+    s = solver(2, prec, mesh)
+    Ui = s.set_state(U.cuda())
+    dts = s.rk_step_adaptive(Ui, cfl, n)
+    Uf = s.set_state(U.cuda())
+    for k in range(n):
+        s.rk_step(Uf, dts[k].item(), 1)
+    assert torch.equal(Ui, Uf)
+    got = s.get_state(Ui).cpu()
+    s.sync()
+    dts = dts.cpu().numpy()
+    # the low-precision runs' states (hence their later step sizes) differ from the fp64
+    # trajectory at the level of their residual error
+    dt_tol = {"fp64": 1e-13, "fp32": 1e-5, "bf16": 1e-4}[prec]
+    assert np.allclose(dts, dts_ref, rtol=dt_tol, atol=0), (dts, dts_ref)
+    err = rel_err(dg, got, ref)
+    print(f"adaptive {prec}: rel L2 error {err:.3e}, dt {dts}")
+    assert err < {"fp64": 1e-12, "fp32": 1e-5, "bf16": 1e-3}[prec]
+
+
 @pytest.mark.parametrize("p", [1, 3])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
 @pytest.mark.parametrize("kind", ["ragged", "bump"])
