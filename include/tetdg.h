@@ -212,6 +212,12 @@ int tdg_rk_stage(tdg_ctx* ctx, const void* U_in, const void* U0, void* U_out, do
 int tdg_residual_vjp_axpy(tdg_ctx* ctx, const void* U, const void* W, double c, int n_terms, const void* const* Y,
                           const double* a, void* Out, void* hip_stream);
 
+/* Admissibility of internal state U: the number of elements where, at some volume
+ * quadrature point, a conserved variable is not finite or the density or pressure is not
+ * positive (n_bad: device int64, overwritten).  A run's failure detector: call it every
+ * few steps and stop when it is non-zero. */
+int tdg_check_state(tdg_ctx* ctx, const void* U, int64_t* n_bad, void* hip_stream);
+
 /* Integrated slip-wall pressure J = sum over slip-wall faces of int_f p(U-) dA (boundary-face
  * quadrature of eq. 11) at internal state U, and optionally dJ/dU (internal layout, overwritten;
  * NULL to skip).  J: device double, overwritten.  The objective of the full configuration's

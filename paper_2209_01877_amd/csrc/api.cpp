@@ -809,6 +809,14 @@ int tdg_stable_dt(tdg_ctx* c, const void* U, double cfl, double* dt, void* s) {
   return e == hipSuccess ? TDG_OK : hip_fail(c, e, "stable dt launch");
 }
 
+int tdg_check_state(tdg_ctx* c, const void* U, int64_t* n_bad, void* s) {
+  int st = require_bound(c);
+  if (st) return st;
+  if (!U || !n_bad) return fail(c, TDG_ERR_INVALID_ARG, "null state or count pointer");
+  hipError_t e = launch_check_state(c->p, c->prec, view(c), refview(c), c->gamma, U, n_bad, (hipStream_t)s);
+  return e == hipSuccess ? TDG_OK : hip_fail(c, e, "check state launch");
+}
+
 int tdg_sync_check(tdg_ctx* c, void* s) {
   if (!c) return TDG_ERR_INVALID_ARG;
   hipError_t e = hipStreamSynchronize((hipStream_t)s);

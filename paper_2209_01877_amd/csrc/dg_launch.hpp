@@ -65,6 +65,8 @@ hipError_t launch_get_state(int p, int prec, const MeshView& m, const void* inte
 hipError_t launch_volume_points(int p, const MeshView& m, const RefView& r, double* xyz, hipStream_t s);
 hipError_t launch_wall_pressure(int p, int prec, const MeshView& m, const RefView& r, double gamma, const void* u,
                                 double* J, void* grad, hipStream_t s);
+hipError_t launch_check_state(int p, int prec, const MeshView& m, const RefView& r, double gamma, const void* u,
+                              int64_t* n_bad, hipStream_t s);
 hipError_t launch_local_dt(int p, int prec, const MeshView& m, double gamma, double cfl, const void* u, double* dt,
                            hipStream_t s);
 hipError_t launch_project(int p, int prec, const MeshView& m, const RefView& r, double gamma, const double* prim,

@@ -200,6 +200,42 @@ hipError_t launch_wall_pressure(int p, int prec, const MeshView& m, const RefVie
   return hipGetLastError();
 }
 
+// Admissibility check: one thread per element evaluates U at the volume quadrature
+// points (fp64) and counts the element once if any value is not finite or the density or
+// pressure there is not positive.  The count accumulates atomically into *n_bad.
+template <class S>
+__global__ void check_state_kernel(MeshView m, int np, int nq, RefView r, double gamma, const S* __restrict__ u,
+                                   unsigned long long* __restrict__ n_bad) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= m.n_elem) return;
+  bool bad = false;
+  for (int q = 0; q < nq && !bad; ++q) {
+    double U[5] = {0, 0, 0, 0, 0};
+    for (int i = 0; i < np; ++i) {
+      const double b = r.B[q * np + i];
+      for (int c = 0; c < 5; ++c) U[c] += b * double(u[sidx(c, i, e, m.epad, npq_of(np))]);
+    }
+    const double p = (gamma - 1.0) * (U[4] - 0.5 * (U[1] * U[1] + U[2] * U[2] + U[3] * U[3]) / U[0]);
+    bool finite = true;
+    for (int c = 0; c < 5; ++c) finite = finite && isfinite(U[c]);
+    bad = !finite || !(U[0] > 0.0) || !(p > 0.0);
+  }
+  if (bad) atomicAdd(n_bad, 1ULL);
+}
+
+hipError_t launch_check_state(int p, int prec, const MeshView& m, const RefView& r, double gamma, const void* u,
+                              int64_t* n_bad, hipStream_t s) {
+  const int np = np_of(p), nq = (p + 1) * (p + 1) * (p + 1);
+  hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(1), 0, s, (unsigned long long*)n_bad, 0ULL);
+  if (prec == 1)
+    hipLaunchKernelGGL(check_state_kernel<float>, dim3(nblocks(m.n_elem, 128)), dim3(128), 0, s, m, np, nq, r, gamma,
+                       (const float*)u, (unsigned long long*)n_bad);
+  else
+    hipLaunchKernelGGL(check_state_kernel<double>, dim3(nblocks(m.n_elem, 128)), dim3(128), 0, s, m, np, nq, r, gamma,
+                       (const double*)u, (unsigned long long*)n_bad);
+  return hipGetLastError();
+}
+
 hipError_t launch_local_dt(int p, int prec, const MeshView& m, double gamma, double cfl, const void* u, double* dt,
                            hipStream_t s) {
   // start from +inf (bit pattern 0x7ff0...); the first atomic minimum replaces it

@@ -234,6 +234,14 @@ class Solver:
               "tdg_stable_dt")
         return dt
 
+    def check_state(self, U: torch.Tensor, stream=None) -> torch.Tensor:
+        """Number of elements with a non-finite value or non-positive density or pressure at a
+        volume quadrature point, as a 0-d device int64 tensor."""
+        self._check_state(U)
+        n = torch.empty((), dtype=torch.int64, device=self.device)
+        check(lib.tdg_check_state(self._ctx, _ptr(U), _ptr(n), _stream(stream)), self._ctx, "tdg_check_state")
+        return n
+
     def sync(self, stream=None) -> None:
         check(lib.tdg_sync_check(self._ctx, _stream(stream)), self._ctx, "tdg_sync_check")
 

@@ -181,6 +181,29 @@ def test_rk_step_adaptive(prec):
     assert err < {"fp64": 1e-12, "fp32": 1e-5, "bf16": 1e-3}[prec]
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_check_state(prec):
+    """Elements with a non-finite value or non-positive density or pressure at a volume point,
+    counted on the GPU, against the count from the oracle's point values."""
+    from oracle import euler
+
+    mesh = make_mesh("ragged")
+    dg = oracle(2, mesh)
+    U = random_state(dg, seed=23)
+    s = solver(2, prec, mesh)
+    assert s.check_state(s.set_state(U.cuda())).item() == 0
+    U[3, 2, 5] = float("nan")                       # non-finite coefficient
+    U[17, 0, 0] = -0.5                              # negative mean density
+    U[40, 4, :] = 0.0                               # zero total energy: negative pressure
+    U[41, 0, 1] = 3.0                               # density negative at some points only
+    Uq = dg.evaluate(U)
+    rho, p = Uq[..., 0], euler.pressure(Uq, 1.4)
+    bad = ~torch.isfinite(Uq).all(-1) | ~(rho > 0) | ~(p > 0)
+    ref = int(bad.any(-1).sum())
+    assert ref == 4
+    assert s.check_state(s.set_state(U.cuda())).item() == ref
+
+
 @pytest.mark.parametrize("p", [1, 3])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
 @pytest.mark.parametrize("kind", ["ragged", "bump"])
