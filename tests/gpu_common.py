@@ -18,6 +18,13 @@ def make_mesh(kind: str):
                          shuffle_seed=2209, vid_seed=2210)
     if kind == "c1":
         return kuhn_cube(4)
+    if kind == "single":      # one tetrahedron, every face on the boundary (3 farfield, 1 wall)
+        from synthetic.mesh import TetMesh
+
+        xyz = np.array([[[0.0, 0.0, 0.0], [0.9, 0.1, 0.0], [0.2, 1.1, 0.1], [0.1, 0.2, 0.8]]])
+        return TetMesh(elem_vid=np.array([[0, 1, 2, 3]], np.int64), elem_xyz=xyz,
+                       bface_vid=np.array([[1, 2, 3], [0, 2, 3], [0, 1, 3], [0, 1, 2]], np.int64),
+                       bface_tag=np.array([1, 2, 1, 1], np.int32), periodic=(False, False, False))
     raise ValueError(kind)
 
 

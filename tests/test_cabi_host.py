@@ -125,6 +125,33 @@ def test_mesh_errors():
     _lib.lib.tdg_destroy(ctx)
 
 
+def test_mesh_size_limits():
+    """An empty mesh and an element count past the kernels' 32-bit element indexing are
+    rejected before any array is read."""
+    ctx = _ctx()
+    one = np.zeros((1, 4), np.int64)
+    xyz = np.zeros((1, 4, 3))
+    assert _lib.lib.tdg_mesh_upload(ctx, 0, one.ctypes.data, xyz.ctypes.data, 0, None, None, 0, None) == -1
+    assert b"n_elem" in _lib.lib.tdg_last_error(ctx)
+    assert _lib.lib.tdg_mesh_upload(ctx, 1 << 31, one.ctypes.data, xyz.ctypes.data, 0, None, None, 0, None) == -1
+    _lib.lib.tdg_destroy(ctx)
+
+
+def test_single_element_mesh():
+    """One tetrahedron with all four faces on the boundary uploads as a valid mesh (one real
+    element in a padded tile, four boundary faces, no interior face)."""
+    ctx = _ctx()
+    xyz = np.array([[[0.0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]]])
+    vid = np.array([[0, 1, 2, 3]], np.int64)
+    bv = np.array([[1, 2, 3], [0, 2, 3], [0, 1, 3], [0, 1, 2]], np.int64)
+    bt = np.array([1, 2, 1, 1], np.int32)
+    assert _lib.lib.tdg_mesh_upload(ctx, 1, vid.ctypes.data, np.ascontiguousarray(xyz).ctypes.data, 4,
+                                    bv.ctypes.data, bt.ctypes.data, 1, None) == 0
+    st = _stats(ctx)
+    assert st[0] == 1 and st[1] % 64 == 0 and st[2] == 0 and st[3] == 4
+    _lib.lib.tdg_destroy(ctx)
+
+
 @pytest.mark.parametrize("mode", ["none", "rcm", "morton", "hilbert"])
 def test_permutation_is_valid(mode):
     m = kuhn_cube(6, shuffle_seed=2209, vid_seed=2210)

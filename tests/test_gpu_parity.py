@@ -149,6 +149,35 @@ def test_stable_dt(prec):
     assert abs(dt - ref) < (1e-14 if prec != "fp32" else 1e-6) * ref
 
 
+@pytest.mark.parametrize("p", [1, 3])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_single_element(p, prec):
+    """Degenerate mesh: one tetrahedron whose four faces are boundary faces (farfield and
+    slip wall), i.e. one live column in a padded 16-element tile."""
+    far = (1.0, 0.5 * math.sqrt(1.4), 0.0, 0.0, 1.0)
+    mesh = make_mesh("single")
+    dg = oracle(p, mesh, far)
+    U = random_state(dg, seed=31)
+    R_ref = dg.residual(U)
+    s = solver(p, prec, mesh, farfield=far)
+    R = gpu_residual(s, U)
+    err = rel_err(dg, R, R_ref)
+    print(f"single element p={p} {prec}: rel L2 error {err:.3e}")
+    assert err < {"fp64": 1e-12, "fp32": 1e-5, "bf16": 5e-2}[prec]
+
+
+def test_zero_steps_leave_state_unchanged():
+    mesh = make_mesh("ragged")
+    dg = oracle(2, mesh)
+    s = solver(2, "bf16", mesh)
+    U = s.set_state(random_state(dg, seed=3).cuda())
+    V = U.clone()
+    s.rk_step(U, 1e-3, 0)
+    dts = s.rk_step_adaptive(U, 0.3, 0)
+    s.sync()
+    assert torch.equal(U, V) and dts.numel() == 0
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
 def test_rk_step_adaptive(prec):
     """Steps sized on the device every step (minimum of the local stable steps of the current
