@@ -645,7 +645,10 @@ template <int P, class Pr>
 static hipError_t launch_stage_impl(const StageArgs& a, hipStream_t stream) {
   using L = Layout<P, Pr::KW>;
   constexpr size_t tab_bytes = sizeof(typename Pr::Op) * L::n_slots * 64;
-  constexpr bool lds = tab_bytes <= 96 * 1024;
+  // stage the tables in LDS when they fit beside the companion staging area in the LDS
+  // share of one workgroup (160 KB per CU over the workgroups resident per CU)
+  constexpr size_t comp_bytes = Pr::mixed ? sizeof(typename Pr::Op) * 4 * 16 * 5 * L::KS * 4 : 0;
+  constexpr bool lds = tab_bytes + comp_bytes <= 160 * 1024 / stage_min_blocks<P, Pr>();
   auto kern = a.flux == 1 ? stage_kernel<P, Pr, lds, true> : stage_kernel<P, Pr, lds, false>;
   int per_cu = 0;
   hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0);
