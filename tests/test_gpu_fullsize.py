@@ -30,3 +30,53 @@ def test_c2_sampled_residual(prec, tol):
     print(f"C2 {prec}: sampled residual rel error {err:.3e}")
     assert err < tol
     assert torch.isfinite(R).all()
+
+
+@pytest.fixture(scope="module")
+def c3():
+    """The benchmark workload: P3 on the 64^3 x 6 (1,572,864 tets) shuffled periodic cube,
+    Hilbert renumbering, with the oracle built once for the sampled checks."""
+    mesh = kuhn_cube(64, length=10.0, shuffle_seed=2209, vid_seed=2210)
+    dg = oracle(3, mesh)
+    rng = np.random.default_rng(1)
+    sample = torch.from_numpy(np.sort(rng.choice(mesh.n_elem, 96, replace=False)))
+    return mesh, dg, sample
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5), ("bf16", 5e-2), ("fp16", 1e-2)])
+def test_c3_sampled_stage(c3, prec, tol):
+    """One SSP-RK3 stage (alpha = 3/4, with U0) at the benchmark size and in the launch
+    configuration the benchmark times, on a random state: sampled elements against
+    alpha U0 + (1 - alpha)(U_in + dt R(U_in)) from the oracle's per-element residual.  The
+    error is measured relative to the stage's residual part (dt = 1)."""
+    mesh, dg, sample = c3
+    U = torch.from_numpy(fields.random_coefficients(mesh.n_elem, dg.Np, seed=21, scale=0.01))
+    U0 = torch.from_numpy(fields.random_coefficients(mesh.n_elem, dg.Np, seed=22, scale=0.01))
+    s = solver(3, prec, mesh, renumber="hilbert")
+    Ui, U0i = s.set_state(U.cuda()), s.set_state(U0.cuda())
+    out = s.rk_stage(Ui, U0i, s.new_state(), 0.75, 1.0)
+    got = s.get_state(out)[sample.cuda()].cpu()
+    s.sync()
+    R_ref = dg.residual(U, sample)
+    if prec == "fp32":  # the stage inputs are stored in fp32
+        U, U0 = U.float().double(), U0.float().double()
+    ref = 0.75 * U0[sample] + 0.25 * (U[sample] + R_ref)
+    err = (got - ref).norm() / (0.25 * R_ref.norm())
+    print(f"C3 {prec}: sampled stage rel error {err:.3e}")
+    assert err < tol
+
+
+@pytest.mark.parametrize("prec,tol", [("bf16", 0.1), ("fp16", 0.02)])
+def test_c3_sampled_residual_vortex(c3, prec, tol):
+    """Mixed precision at the benchmark size on the benchmark's smooth state (the projected
+    isentropic vortex): sampled residuals against the oracle (stated error)."""
+    mesh, dg, sample = c3
+    s64 = solver(3, "fp64", mesh, renumber="hilbert")
+    U = s64.get_state(s64.project_fn(lambda x: fields.isentropic_vortex(x, length=10.0))).cpu()
+    s = solver(3, prec, mesh, renumber="hilbert")
+    R = s.get_state(s.residual(s.set_state(U.cuda())))[sample.cuda()].cpu()
+    s.sync()
+    R_ref = dg.residual(U, sample)
+    err = (R - R_ref).norm() / R_ref.norm()
+    print(f"C3 vortex {prec}: sampled residual rel error {err:.3e}")
+    assert err < tol
