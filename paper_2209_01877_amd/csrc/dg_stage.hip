@@ -598,23 +598,38 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
   }
 }
 
-// Operand companion of an fp64 state (mixed modes): one thread per (element, variable).
+// Operand companion of an fp64 state (mixed modes).  A workgroup packs 64 consecutive
+// elements (E_pad is a multiple of 64): the fp64 mode quads are read with the element
+// index fastest (contiguous 32-byte quads), converted into the records in LDS, and the
+// 64 records, contiguous in q, leave as 16-byte slots.
 template <int P, class Pr>
-__global__ void pack_kernel(MeshView m, const double* __restrict__ u, typename Pr::E1* __restrict__ q,
-                            float* __restrict__ c0) {
+__global__ __launch_bounds__(256) void pack_kernel(MeshView m, const double* __restrict__ u,
+                                                   typename Pr::E1* __restrict__ q, float* __restrict__ c0) {
+  using E1 = typename Pr::E1;
   using O = Ord<P>;
-  constexpr int NP = O::NP, KS = Layout<P, 8>::KS;
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= m.epad * 5) return;
-  const int64_t e = t / 5;
-  const int v = (int)(t % 5);
-  typename Pr::E1* dst = q + (e * 5 + v) * (32 * KS);
+  constexpr int NP = O::NP, REC = 32 * Layout<P, 8>::KS, NPQ = npq_of(NP), RQ = REC / 4;
+  __shared__ E1 rec[64 * 5 * REC];
+  const int64_t e0 = (int64_t)blockIdx.x * 64;
+  for (int i = threadIdx.x; i < 5 * RQ * 64; i += blockDim.x) {
+    const int el = i % 64, k = (i / 64) % RQ, v = i / (64 * RQ);
+    const int64_t e = e0 + el;
+    typedef double d4v_t __attribute__((ext_vector_type(4)));
+    d4v_t x = {0.0, 0.0, 0.0, 0.0};
+    if (k < NPQ) x = *reinterpret_cast<const d4v_t*>(u + ((int64_t)(v * NPQ + k) * m.epad + e) * 4);
+    typedef E1 e4v_t __attribute__((ext_vector_type(4)));
+    e4v_t h;
 #pragma unroll
-  for (int mode = 0; mode < 32 * KS; ++mode) {
-    const float x = (mode > 0 && mode < NP) ? float(u[sidx(v, mode, e, m.epad, npq_of(NP))]) : 0.0f;
-    dst[mode] = (typename Pr::E1)x;
+    for (int j = 0; j < 4; ++j) {
+      const int mode = 4 * k + j;
+      h[j] = (E1)((mode > 0 && mode < NP) ? float(x[j]) : 0.0f);
+    }
+    *reinterpret_cast<e4v_t*>(rec + (el * 5 + v) * REC + 4 * k) = h;
+    if (k == 0) c0[v * m.epad + e] = float(x[0]);
   }
-  c0[v * m.epad + e] = float(u[sidx(v, 0, e, m.epad, npq_of(NP))]);
+  __syncthreads();
+  const uint4* src = reinterpret_cast<const uint4*>(rec);
+  uint4* dst = reinterpret_cast<uint4*>(q + e0 * 5 * REC);
+  for (int i = threadIdx.x; i < 64 * 5 * REC * (int)sizeof(E1) / 16; i += blockDim.x) dst[i] = src[i];
 }
 
 size_t companion_bytes(int p, int64_t epad) {
@@ -625,7 +640,8 @@ size_t companion_bytes(int p, int64_t epad) {
 }
 
 hipError_t launch_pack(int p, int prec, const MeshView& m, const void* u, void* q, float* c0, hipStream_t s) {
-  const unsigned nb = (unsigned)((m.epad * 5 + 255) / 256);
+  if (m.epad % 64 != 0) return hipErrorInvalidValue;
+  const unsigned nb = (unsigned)(m.epad / 64);
 #define TDG_PACK(PP)                                                                                          \
   if (p == PP) {                                                                                             \
     if (prec == 2)                                                                                           \
