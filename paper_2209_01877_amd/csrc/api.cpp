@@ -101,6 +101,10 @@ void pack_stage(const RefElem& R, int prec, std::vector<unsigned char>& out) {
   };
   auto kmode = [&](int s, int g, int m) { return KW == 1 ? K * s + g : K * s + 8 * g + m; };
   auto mode_ok = [&](int mode) { return mode < NP && !(mixed && mode == 0); };
+  // fp32, last mode tile of at most 4 modes: 4x4x1 block operands (lane row r supplies
+  // mode 16 mt + r % 4; the stage kernel's kTail4)
+  const bool tail4 = prec == TDG_FP32 && NP - 16 * (O::MT - 1) <= 4;
+  auto tile_mode = [&](int mt, int r) { return 16 * mt + ((tail4 && mt == O::MT - 1) ? r % 4 : r); };
   // interp
   for (int qt = 0; qt < O::QT; ++qt)
     for (int s = 0; s < KS; ++s)
@@ -124,7 +128,7 @@ void pack_stage(const RefElem& R, int prec, std::vector<unsigned char>& out) {
     for (int qt = 0; qt < O::QT; ++qt)
       for (int pk = 0; pk < PK; ++pk)
         slot([&](int r, int g, int m) {
-          const int mode = 16 * mt + r;
+          const int mode = tile_mode(mt, r);
           int d, j;
           if (!mixed) {
             d = pk / 4;
@@ -145,7 +149,7 @@ void pack_stage(const RefElem& R, int prec, std::vector<unsigned char>& out) {
       for (int ft = 0; ft < O::FT; ++ft)
         for (int lk = 0; lk < LK; ++lk)
           slot([&](int r, int g, int m) {
-            const int mode = 16 * mt + r;
+            const int mode = tile_mode(mt, r);
             int j = lk;
             if (mixed) {
               if (m >= 4) return 0.0;

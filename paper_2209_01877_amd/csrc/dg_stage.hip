@@ -100,6 +100,17 @@ struct LiftPair<Pr, true> {
   typedef E1 type __attribute__((ext_vector_type(2)));
 };
 
+// Projection / lift MFMA for one mode tile: the 4x4x1 block form for the short last
+// tile of the fp32 path (see kTail4), else the precision's 16x16 instruction.
+template <class Pr, bool kTail4>
+__device__ __forceinline__ typename Pr::Acc mfma_tile(bool last, typename Pr::Op a, typename Pr::Op b,
+                                                      typename Pr::Acc c) {
+  if constexpr (kTail4) {
+    if (last) return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
+  }
+  return Pr::mfma(a, b, c);
+}
+
 template <int P, class Pr>
 constexpr int stage_min_blocks() {
   return (P <= 3 && !Pr::f64) ? 2 : 1;
@@ -137,6 +148,11 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
   const MeshView& mv = a.mesh;
   const int64_t epad = mv.epad;
   constexpr int NPQ = npq_of(NP);
+  // fp32: when the last mode tile holds at most 4 modes (P1, P3, P4), its projection and
+  // lift run as 4x4x1 MFMA blocks (a quarter of the 16x16x4 cost): lane group g
+  // accumulates its own points' share of those modes for its 16 elements, and the four
+  // shares are summed across lane groups before the epilogue
+  constexpr bool kTail4 = Pr::KW == 1 && !Pr::f64 && NP - 16 * (MT - 1) <= 4;
   const uint32_t quad_bytes = (uint32_t)(epad * 4 * sizeof(S));  // one (variable, mode quad) plane
   const uint32_t var_bytes = quad_bytes * NPQ;
   const T gamma = T(a.gamma), gm1 = T(a.gamma - 1.0);
@@ -267,7 +283,7 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
             for (int dd = 0; dd < 3; ++dd) {
               const Op av = tab[L::proj(mt, qt, 4 * dd + j) * 64 + lane];
 #pragma unroll
-              for (int v = 0; v < 5; ++v) acc[mt][v] = Pr::mfma(av, Pr::op1(yy[dd][v]), acc[mt][v]);
+              for (int v = 0; v < 5; ++v) acc[mt][v] = mfma_tile<Pr, kTail4>(mt == MT - 1, av, Pr::op1(yy[dd][v]), acc[mt][v]);
             }
         }
       } else {
@@ -390,7 +406,7 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
             for (int lk = 0; lk < 4; ++lk) {
               const Op av = tab[L::lift(mt, f, ft, lk) * 64 + lane];
 #pragma unroll
-              for (int v = 0; v < 5; ++v) acc[mt][v] = Pr::mfma(av, Pr::op1(fh[v][lk]), acc[mt][v]);
+              for (int v = 0; v < 5; ++v) acc[mt][v] = mfma_tile<Pr, kTail4>(mt == MT - 1, av, Pr::op1(fh[v][lk]), acc[mt][v]);
             }
         } else {
 #pragma unroll
@@ -416,6 +432,18 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
     // tile.  Lane group g supplies k = g (volume direction g, or face 0 for g = 3) and
     // k = 4 + g (face g + 1, or zero); the table rows are permuted so that the fp64
     // accumulator rows line up with the fp32 accumulator rows of the same lane.
+    if constexpr (kTail4) {
+      // sum the lane groups' shares of the last tile: lane group 0 then holds its modes
+#pragma unroll
+      for (int v = 0; v < 5; ++v)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          float x = acc[MT - 1][v][j];
+          x += __shfl_xor(x, 16);
+          x += __shfl_xor(x, 32);
+          acc[MT - 1][v][j] = x;
+        }
+    }
     // Every lane takes part in the epilogue's MFMAs (the A operand rows are spread over
     // all lanes); only the stores are limited to the mesh's elements.
     const bool live = e < mv.n_elem;
