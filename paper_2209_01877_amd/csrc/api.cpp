@@ -101,9 +101,10 @@ void pack_stage(const RefElem& R, int prec, std::vector<unsigned char>& out) {
   };
   auto kmode = [&](int s, int g, int m) { return KW == 1 ? K * s + g : K * s + 8 * g + m; };
   auto mode_ok = [&](int mode) { return mode < NP && !(mixed && mode == 0); };
-  // fp32, last mode tile of at most 4 modes: 4x4x1 block operands (lane row r supplies
-  // mode 16 mt + r % 4; the stage kernel's kTail4)
-  const bool tail4 = prec == TDG_FP32 && NP - 16 * (O::MT - 1) <= 4;
+  // FP32 / FP64, last mode tile of at most 4 modes: lane row r supplies mode 16 mt + r % 4
+  // (4x4x1 block operands in fp32; in fp64 lanes 16 g + 0..3 hold the four values of lane
+  // group g's point; the stage kernel's kTail4)
+  const bool tail4 = !mixed && NP - 16 * (O::MT - 1) <= 4;
   auto tile_mode = [&](int mt, int r) { return 16 * mt + ((tail4 && mt == O::MT - 1) ? r % 4 : r); };
   // interp
   for (int qt = 0; qt < O::QT; ++qt)

@@ -101,14 +101,30 @@ struct LiftPair<Pr, true> {
 };
 
 // Projection / lift MFMA for one mode tile: the 4x4x1 block form for the short last
-// tile of the fp32 path (see kTail4), else the precision's 16x16 instruction.
+// tile of the fp32 path (see kTail4; fp64 handles that tile with tail_fma), else the
+// precision's 16x16 instruction.
 template <class Pr, bool kTail4>
 __device__ __forceinline__ typename Pr::Acc mfma_tile(bool last, typename Pr::Op a, typename Pr::Op b,
                                                       typename Pr::Acc c) {
-  if constexpr (kTail4) {
+  if constexpr (kTail4 && !Pr::f64) {
     if (last) return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
   }
   return Pr::mfma(a, b, c);
+}
+
+// FP64 short last tile: acc[v][r] += A[r] y[v] for the tile's modes r = 0..3, with the
+// four table values of this lane group's point read once (a broadcast within the group).
+template <class Pr>
+__device__ __forceinline__ void tail_fma(const typename Pr::Op* __restrict__ t, const typename Pr::T (&y)[5],
+                                         typename Pr::Acc (&acc)[5]) {
+  const double a0 = t[0], a1 = t[1], a2 = t[2], a3 = t[3];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    acc[v][0] = __builtin_fma(a0, y[v], acc[v][0]);
+    acc[v][1] = __builtin_fma(a1, y[v], acc[v][1]);
+    acc[v][2] = __builtin_fma(a2, y[v], acc[v][2]);
+    acc[v][3] = __builtin_fma(a3, y[v], acc[v][3]);
+  }
 }
 
 template <int P, class Pr>
@@ -148,11 +164,13 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
   const MeshView& mv = a.mesh;
   const int64_t epad = mv.epad;
   constexpr int NPQ = npq_of(NP);
-  // fp32: when the last mode tile holds at most 4 modes (P1, P3, P4), its projection and
-  // lift run as 4x4x1 MFMA blocks (a quarter of the 16x16x4 cost): lane group g
-  // accumulates its own points' share of those modes for its 16 elements, and the four
-  // shares are summed across lane groups before the epilogue
-  constexpr bool kTail4 = Pr::KW == 1 && !Pr::f64 && NP - 16 * (MT - 1) <= 4;
+  // FP32 / FP64: when the last mode tile holds at most 4 modes (P1, P3, P4), a 16-row MFMA
+  // would waste 12 of its rows.  Its projection and lift instead let lane group g
+  // accumulate its own points' share of those modes for its 16 elements — as 4x4x1 MFMA
+  // blocks in fp32 (a quarter of the 16x16x4 cost), as fp64 FMAs with the four table
+  // values read once per lane group — and the four shares are summed across lane groups
+  // before the epilogue.
+  constexpr bool kTail4 = Pr::KW == 1 && NP - 16 * (MT - 1) <= 4;
   const uint32_t quad_bytes = (uint32_t)(epad * 4 * sizeof(S));  // one (variable, mode quad) plane
   const uint32_t var_bytes = quad_bytes * NPQ;
   const T gamma = T(a.gamma), gm1 = T(a.gamma - 1.0);
@@ -281,6 +299,12 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
           for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
             for (int dd = 0; dd < 3; ++dd) {
+              if constexpr (kTail4 && Pr::f64) {
+                if (mt == MT - 1) {
+                  tail_fma<Pr>(tab + L::proj(mt, qt, 4 * dd + j) * 64 + 16 * g, yy[dd], acc[mt]);
+                  continue;
+                }
+              }
               const Op av = tab[L::proj(mt, qt, 4 * dd + j) * 64 + lane];
 #pragma unroll
               for (int v = 0; v < 5; ++v) acc[mt][v] = mfma_tile<Pr, kTail4>(mt == MT - 1, av, Pr::op1(yy[dd][v]), acc[mt][v]);
@@ -404,6 +428,15 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
           for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
             for (int lk = 0; lk < 4; ++lk) {
+              if constexpr (kTail4 && Pr::f64) {
+                if (mt == MT - 1) {
+                  T fl[5];
+#pragma unroll
+                  for (int v = 0; v < 5; ++v) fl[v] = fh[v][lk];
+                  tail_fma<Pr>(tab + L::lift(mt, f, ft, lk) * 64 + 16 * g, fl, acc[mt]);
+                  continue;
+                }
+              }
               const Op av = tab[L::lift(mt, f, ft, lk) * 64 + lane];
 #pragma unroll
               for (int v = 0; v < 5; ++v) acc[mt][v] = mfma_tile<Pr, kTail4>(mt == MT - 1, av, Pr::op1(fh[v][lk]), acc[mt][v]);
@@ -433,16 +466,26 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
     // k = 4 + g (face g + 1, or zero); the table rows are permuted so that the fp64
     // accumulator rows line up with the fp32 accumulator rows of the same lane.
     if constexpr (kTail4) {
-      // sum the lane groups' shares of the last tile: lane group 0 then holds its modes
+      // sum the lane groups' shares of the last tile (register r: mode 16 (MT - 1) + r) and
+      // move them to the accumulator rows of the precision: fp32 row 4 g + j (lane group 0
+      // holds the tile's modes in its registers), fp64 row g + 4 j (mode r in register 0
+      // of lane group r)
 #pragma unroll
-      for (int v = 0; v < 5; ++v)
+      for (int v = 0; v < 5; ++v) {
+        T x[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          float x = acc[MT - 1][v][j];
-          x += __shfl_xor(x, 16);
-          x += __shfl_xor(x, 32);
-          acc[MT - 1][v][j] = x;
+          x[j] = acc[MT - 1][v][j];
+          x[j] += __shfl_xor(x[j], 16);
+          x[j] += __shfl_xor(x[j], 32);
         }
+        if constexpr (Pr::f64) {
+          acc[MT - 1][v] = Acc{g == 0 ? x[0] : g == 1 ? x[1] : g == 2 ? x[2] : x[3], 0.0, 0.0, 0.0};
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[MT - 1][v][j] = x[j];
+        }
+      }
     }
     // Every lane takes part in the epilogue's MFMAs (the A operand rows are spread over
     // all lanes); only the stores are limited to the mesh's elements.
