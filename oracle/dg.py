@@ -33,8 +33,10 @@ GAMMA = 1.4
 class DG:
     def __init__(self, p: int, elem_vid, elem_xyz, bface_vid=None, bface_tag=None,
                  gamma: float = GAMMA, farfield_prim=(1.0, 0.5 * np.sqrt(1.4), 0.0, 0.0, 1.0),
-                 chunk: int = 65536, flux: str = "rusanov"):
+                 chunk: int = 65536, flux: str = "rusanov", mu: float = 0.0, prandtl: float = 0.72):
         self.p = p
+        self.mu = mu
+        self.prandtl = prandtl
         self.gamma = gamma
         self.chunk = chunk
         self.flux = flux
@@ -139,9 +141,97 @@ class DG:
         return S
 
     def residual(self, U: torch.Tensor, elems: torch.Tensor | None = None) -> torch.Tensor:
-        """R(U) = (V - S)/|K|, user layout (E, 5, Np) float64; optionally only for `elems`."""
+        """R(U) = (V - S)/|K|, user layout (E, 5, Np) float64; optionally only for `elems`.
+        With mu > 0 the viscous terms of eq. 11 are included: R = (V - S - Vv + Sv)/|K|."""
         vol = self.volume if elems is None else self.volume[elems]
-        return (self.volume_term(U, elems) - self.face_term(U, elems)) / vol[:, None, None]
+        R = self.volume_term(U, elems) - self.face_term(U, elems)
+        if self.mu > 0.0:
+            R = R - self.viscous_term(U, self.gradient(U), elems)
+        return R / vol[:, None, None]
+
+    # --------------------------------------------------- viscous terms (BR1)
+    def _face_traces(self, U: torch.Tensor, fi: torch.Tensor):
+        """Traces of U on faces fi from both sides, with the inviscid ghost on boundary faces."""
+        em, fm, ep, fp, tag = self.f_em[fi], self.f_fm[fi], self.f_ep[fi], self.f_fp[fi], self.f_tag[fi]
+        n = self.f_n[fi][:, None, :]
+        Bm, Bp = self.Bf[fm], self.Bf[fp.clamp(min=0)]
+        Um = torch.einsum("fqi,fvi->fqv", Bm, U[em])
+        Up = torch.einsum("fqi,fvi->fqv", Bp, U[ep.clamp(min=0)])
+        interior = ep >= 0
+        if not bool(interior.all()):
+            far = self.farfield.expand_as(Um)
+            wall = euler.slipwall_ghost(Um, n.expand(Um.shape[:-1] + (3,)))
+            ghost = torch.where((tag == 2)[:, None, None], wall, far)
+            Up = torch.where(interior[:, None, None], Up, ghost)
+        return em, ep, Bm, Bp, Um, Up, interior
+
+    def gradient(self, U: torch.Tensor) -> torch.Tensor:
+        """BR1 auxiliary variable Z = grad U, modal, (E, 3, 5, Np):
+        |K| Z_i = -integral_K U grad phi_i + sum_f integral_f (U- + U+)/2 n phi_i
+        (the first equation of eq. 11 with the central interface value of Bassi and Rebay)."""
+        Z = torch.zeros((self.n_elem, 3) + tuple(U.shape[1:]), dtype=U.dtype)
+        for s in range(0, self.n_elem, self.chunk):
+            ks = torch.arange(s, min(s + self.chunk, self.n_elem))
+            Uq = torch.einsum("qi,evi->eqv", self.B, U[ks])
+            # d phi_i / d x_e = sum_d D_d jinv[d][e]
+            Z[ks] -= self.absdet[ks, None, None, None] * torch.einsum(
+                "q,dqi,kde,kqv->kevi", self.w, self.D, self.jinv[ks], Uq)
+        for s in range(0, self.f_em.shape[0], self.chunk):
+            fi = torch.arange(s, min(s + self.chunk, self.f_em.shape[0]))
+            em, ep, Bm, Bp, Um, Up, interior = self._face_traces(U, fi)
+            Uh = 0.5 * (Um + Up)
+            scale = 2.0 * self.f_area[fi][:, None]
+            n = self.f_n[fi]
+            Zm = scale[:, :, None, None] * torch.einsum("q,fqi,fqv,fe->fevi", self.wf, Bm, Uh, n)
+            Zp = scale[:, :, None, None] * torch.einsum("q,fqi,fqv,fe->fevi", self.wf, Bp, Uh, n)
+            Z = Z.index_add(0, em, Zm)
+            Z = Z.index_add(0, ep[interior], -Zp[interior])
+        return Z / self.volume[:, None, None, None]
+
+    def viscous_term(self, U: torch.Tensor, Z: torch.Tensor, elems: torch.Tensor | None = None) -> torch.Tensor:
+        """Vv - Sv with Vv_i = integral_K F_v(U, Z) . grad phi_i and
+        Sv_i = sum_f integral_f (F_v(U-, Z-) + F_v(U+, Z+))/2 . n phi_i (BR1; on boundary
+        faces U+ is the inviscid ghost and Z+ = Z-); rows follow `elems`."""
+        from .viscous import viscous_flux
+
+        idx = torch.arange(self.n_elem) if elems is None else elems
+        out = []
+        for s in range(0, idx.shape[0], self.chunk):
+            ks = idx[s:s + self.chunk]
+            Uq = torch.einsum("qi,evi->eqv", self.B, U[ks])
+            Zq = torch.einsum("qi,kevi->kqev", self.B, Z[ks])
+            Fv = viscous_flux(Uq, Zq, self.gamma, self.mu, self.prandtl)      # (k, q, j, v)
+            G = torch.einsum("kde,kqev->kqdv", self.jinv[ks], Fv)
+            out.append(self.absdet[ks, None, None] * torch.einsum("q,dqi,kqdv->kvi", self.w, self.D, G))
+        Vv = torch.cat(out, 0)
+        if elems is None:
+            row = torch.arange(self.n_elem)
+            faces = torch.arange(self.f_em.shape[0])
+        else:
+            row = torch.full((self.n_elem,), -1, dtype=torch.long)
+            row[elems] = torch.arange(elems.shape[0])
+            touch = (row[self.f_em] >= 0) | ((self.f_ep >= 0) & (row[self.f_ep.clamp(min=0)] >= 0))
+            faces = torch.nonzero(touch).flatten()
+        Sv = torch.zeros_like(Vv)
+        for s in range(0, faces.shape[0], self.chunk):
+            fi = faces[s:s + self.chunk]
+            em, ep, Bm, Bp, Um, Up, interior = self._face_traces(U, fi)
+            fm, fp = self.f_fm[fi], self.f_fp[fi]
+            Zm = torch.einsum("fqi,fevi->fqev", Bm, Z[em])
+            Zp = torch.einsum("fqi,fevi->fqev", Bp, Z[ep.clamp(min=0)])
+            Zp = torch.where(interior[:, None, None, None], Zp, Zm)
+            n = self.f_n[fi][:, None, :]
+            Fm = viscous_flux(Um, Zm, self.gamma, self.mu, self.prandtl)
+            Fp = viscous_flux(Up, Zp, self.gamma, self.mu, self.prandtl)
+            H = 0.5 * torch.einsum("fqjv,fqj->fqv", Fm + Fp, n.expand(Um.shape[:-1] + (3,)))
+            scale = 2.0 * self.f_area[fi][:, None, None]
+            Sm = scale * torch.einsum("q,fqi,fqv->fvi", self.wf, Bm, H)
+            Sp = scale * torch.einsum("q,fqi,fqv->fvi", self.wf, Bp, H)
+            rm = row[em]
+            rp = torch.where(interior, row[ep.clamp(min=0)], torch.full_like(ep, -1))
+            Sv = Sv.index_add(0, rm[rm >= 0], Sm[rm >= 0])
+            Sv = Sv.index_add(0, rp[rp >= 0], -Sp[rp >= 0])
+        return Vv - Sv
 
     def wall_pressure(self, U: torch.Tensor) -> torch.Tensor:
         """Integrated slip-wall pressure, sum over wall faces of 2 A_f sum_q w_q p(U-_q).
