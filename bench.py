@@ -30,7 +30,7 @@ from synthetic import fields, kuhn_cube  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_kernel_p3_64cube_traffic.json")
-KERNEL_SOURCES = ["dg_stage.hip", "dg_kernels.hpp", "dg_common.hpp", "dg_launch.hpp"]
+KERNEL_SOURCES = ["dg_stage.hip", "dg_kernels.hpp", "dg_common.hpp", "dg_launch.hpp", "dg_tile.hpp"]
 
 
 def kernel_source_hash() -> str:

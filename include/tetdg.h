@@ -129,6 +129,20 @@ int tdg_mesh_bind(tdg_ctx* ctx, void* dev_buf, size_t bytes, void* hip_stream);
  * stages and the adjoint entry points all use the selected flux. */
 int tdg_set_flux(tdg_ctx* ctx, int flux);
 
+/* Viscous (Navier-Stokes) terms of eqs. 1 and 11 with constant dynamic viscosity mu and
+ * Prandtl number Pr (mu = 0: Euler, the default).  The paper's BR1 form: the auxiliary
+ * variable Z = grad U is lifted with central interface values, and the viscous interface
+ * flux is the average of both sides' viscous fluxes; boundary faces use the inviscid
+ * ghost state with Z+ = Z-.  Stress by Stokes' hypothesis, heat flux -kappa grad T with
+ * kappa = mu gamma / ((gamma - 1) Pr) and T = p / rho.  Every residual and RK entry point
+ * then includes them (two more launches per stage: the lifting and the viscous residual
+ * part, which the stage kernel adds).  Must be called before tdg_mesh_upload (the device
+ * buffer then holds their scratch: four more states).  FP64 and FP32 modes; the mixed
+ * modes return TDG_ERR_UNSUPPORTED, and so do the adjoint entry points while mu > 0.
+ * tdg_stable_dt stays the inviscid rule (the caller bounds dt by the viscous limit).
+ * Errors: TDG_ERR_INVALID_ARG (mu < 0, Pr <= 0), TDG_ERR_STATE (mesh already uploaded). */
+int tdg_set_viscosity(tdg_ctx* ctx, double mu, double prandtl);
+
 /* Free-stream primitive state (rho, u, v, w, p) used as the farfield ghost (host array). */
 int tdg_set_farfield(tdg_ctx* ctx, const double prim[5]);
 

@@ -47,6 +47,7 @@ _SIGS = {
     "tdg_rk_step": (_i, [_p, _p, _p, _d, _i, _p]),
     "tdg_rk_step_adaptive": (_i, [_p, _p, _p, _d, _i, _p, _p]),
     "tdg_check_state": (_i, [_p, _p, _p, _p]),
+    "tdg_set_viscosity": (_i, [_p, _d, _d]),
     "tdg_residual_vjp": (_i, [_p, _p, _p, _p, _p]),
     "tdg_work_bytes": (_i, [_p, ctypes.POINTER(_sz)]),
     "tdg_rk_stage": (_i, [_p, _p, _p, _p, _d, _d, _p]),

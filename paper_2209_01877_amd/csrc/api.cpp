@@ -37,6 +37,9 @@ struct tdg_ctx {
          off_mom = 0, off_mtab = 0, off_qx = 0, off_qw = 0, off_B = 0, off_fw = 0, off_Bf = 0, off_comp = 0, total = 0;
   double far[5] = {1.0, 0.0, 0.0, 0.0, 2.5};
   int flux = TDG_FLUX_RUSANOV;
+  // viscous (Navier-Stokes, BR1) terms: off when mu == 0; scratch Z (3 states) and Rv
+  double mu = 0.0, prandtl = 0.72;
+  size_t off_z = 0, off_rv = 0;
 };
 
 namespace {
@@ -458,6 +461,12 @@ int tdg_mesh_upload(tdg_ctx* c, int64_t n_elem, const int64_t* elem_vid, const d
     c->off_Bf = take(c->ref.Bf.size() * sizeof(double));
     // mixed modes: scratch operand companion for single residual / stage calls
     c->off_comp = take(c->prec >= TDG_MIXED_BF16 ? companion_bytes(c->p, epad) : 0);
+    // viscous scratch: Z = grad U (15 state-layout variables) and the viscous residual part
+    {
+      const size_t sb = (size_t)5 * ((c->ref.np + 3) / 4) * epad * 4 * (c->prec == TDG_FP32 ? 4 : 8);
+      c->off_z = take(c->mu > 0.0 ? 3 * sb : 0);
+      c->off_rv = take(c->mu > 0.0 ? sb : 0);
+    }
     c->total = off;
     c->has_mesh = true;
     c->bound = false;
@@ -520,6 +529,18 @@ int tdg_set_flux(tdg_ctx* c, int flux) {
   if (!c) return TDG_ERR_INVALID_ARG;
   if (flux != TDG_FLUX_RUSANOV && flux != TDG_FLUX_ROE) return fail(c, TDG_ERR_INVALID_ARG, "unknown flux");
   c->flux = flux;
+  return TDG_OK;
+}
+
+int tdg_set_viscosity(tdg_ctx* c, double mu, double prandtl) {
+  if (!c) return TDG_ERR_INVALID_ARG;
+  if (!(mu >= 0.0) || !std::isfinite(mu) || !(prandtl > 0.0) || !std::isfinite(prandtl))
+    return fail(c, TDG_ERR_INVALID_ARG, "mu must be >= 0 and the Prandtl number > 0");
+  if (c->has_mesh) return fail(c, TDG_ERR_STATE, "set the viscosity before tdg_mesh_upload (it sizes the device buffer)");
+  if (mu > 0.0 && c->prec >= TDG_MIXED_BF16)
+    return fail(c, TDG_ERR_UNSUPPORTED, "viscous terms are implemented for the FP64 and FP32 modes");
+  c->mu = mu;
+  c->prandtl = prandtl;
   return TDG_OK;
 }
 
@@ -624,6 +645,30 @@ int tdg_work_bytes(const tdg_ctx* c, size_t* bytes) {
   return TDG_OK;
 }
 
+// Viscous terms of U (mu > 0): Z = grad U, then the viscous residual part into the
+// context's scratch, which the next stage launch adds to R through a.r_add.
+static hipError_t viscous_part(tdg_ctx* c, const void* U, StageArgs& a, hipStream_t s) {
+  a.r_add = nullptr;
+  if (!(c->mu > 0.0)) return hipSuccess;
+  ViscArgs v;
+  std::memset(&v, 0, sizeof(v));
+  v.u = U;
+  v.z = c->dev + c->off_z;
+  v.out = c->dev + c->off_z;
+  v.mesh = view(c);
+  v.tab = c->dev + c->off_stab;
+  v.gamma = c->gamma;
+  v.mu = c->mu;
+  v.prandtl = c->prandtl;
+  for (int k = 0; k < 5; ++k) v.far[k] = c->far[k];
+  hipError_t e = launch_grad(c->p, c->prec, v, s);
+  if (e != hipSuccess) return e;
+  v.out = c->dev + c->off_rv;
+  e = launch_visc(c->p, c->prec, v, s);
+  a.r_add = c->dev + c->off_rv;
+  return e;
+}
+
 int tdg_residual(tdg_ctx* c, const void* U, void* R, void* s) {
   int st = require_bound(c);
   if (st) return st;
@@ -633,6 +678,8 @@ int tdg_residual(tdg_ctx* c, const void* U, void* R, void* s) {
     hipError_t e = pack_scratch(c, U, a, (hipStream_t)s);
     if (e != hipSuccess) return hip_fail(c, e, "pack launch");
   }
+  hipError_t ev = viscous_part(c, U, a, (hipStream_t)s);
+  if (ev != hipSuccess) return hip_fail(c, ev, "viscous launch");
   a.u_in = U;
   a.u0 = U;
   a.u_out = R;
@@ -677,7 +724,9 @@ int tdg_rk_step(tdg_ctx* c, void* U, void* work, double dt, int n_steps, void* s
       a.c0_in = c0[qin[stg]];
       a.q_out = q[qout[stg]];
       a.c0_out = c0[qout[stg]];
-      hipError_t e = launch_stage(c->p, c->prec, a, (hipStream_t)s);
+      hipError_t e = viscous_part(c, a.u_in, a, (hipStream_t)s);
+      if (e != hipSuccess) return hip_fail(c, e, "viscous launch");
+      e = launch_stage(c->p, c->prec, a, (hipStream_t)s);
       if (e != hipSuccess) return hip_fail(c, e, "rk stage launch");
     }
   }
@@ -723,6 +772,8 @@ int tdg_rk_step_adaptive(tdg_ctx* c, void* U, void* work, double cfl, int n_step
       a.c0_in = c0[qin[stg]];
       a.q_out = q[qout[stg]];
       a.c0_out = c0[qout[stg]];
+      e = viscous_part(c, a.u_in, a, (hipStream_t)s);
+      if (e != hipSuccess) return hip_fail(c, e, "viscous launch");
       e = launch_stage(c->p, c->prec, a, (hipStream_t)s);
       if (e != hipSuccess) return hip_fail(c, e, "rk stage launch");
     }
@@ -747,6 +798,8 @@ int tdg_rk_stage(tdg_ctx* c, const void* U_in, const void* U0, void* U_out, doub
   a.u_in = U_in;
   a.u0 = U0;
   a.u_out = U_out;
+  hipError_t ev = viscous_part(c, U_in, a, (hipStream_t)s);
+  if (ev != hipSuccess) return hip_fail(c, ev, "viscous launch");
   hipError_t e = launch_stage(c->p, c->prec, a, (hipStream_t)s);
   return e == hipSuccess ? TDG_OK : hip_fail(c, e, "rk stage launch");
 }
@@ -755,6 +808,7 @@ int tdg_residual_vjp_axpy(tdg_ctx* c, const void* U, const void* W, double cw, i
                           const double* ya, void* Out, void* s) {
   int st = require_bound(c);
   if (st) return st;
+  if (c->mu > 0.0) return fail(c, TDG_ERR_UNSUPPORTED, "the adjoint covers the inviscid residual (viscosity is set)");
   if (!U || !W || !Out || Out == U || Out == W) return fail(c, TDG_ERR_INVALID_ARG, "U, W, Out must be distinct");
   if (n_terms < 0 || n_terms > 3 || (n_terms > 0 && (!Y || !ya))) return fail(c, TDG_ERR_INVALID_ARG, "bad terms");
   VjpArgs a;
@@ -781,6 +835,7 @@ int tdg_residual_vjp_axpy(tdg_ctx* c, const void* U, const void* W, double cw, i
 int tdg_residual_vjp(tdg_ctx* c, const void* U, const void* W, void* Ubar, void* s) {
   int st = require_bound(c);
   if (st) return st;
+  if (c->mu > 0.0) return fail(c, TDG_ERR_UNSUPPORTED, "the adjoint covers the inviscid residual (viscosity is set)");
   if (!U || !W || !Ubar || Ubar == U || Ubar == W) return fail(c, TDG_ERR_INVALID_ARG, "U, W, Ubar must be distinct");
   VjpArgs a;
   std::memset(&a, 0, sizeof(a));

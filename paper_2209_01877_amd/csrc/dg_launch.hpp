@@ -11,6 +11,7 @@ struct StageArgs {
   const void* u0;     // RK stage base state (may be null when alpha == 0)
   void* u_out;        // residual or stage result
   double alpha, dt;   // U_out = alpha U0 + (1 - alpha)(U_in + dt R)
+  const void* r_add;  // when non-null, a residual part added to R (state layout, S): the viscous terms
   const double* dt_dev;  // when non-null, dt is read from this device scalar instead
   int rk;             // 0: store R, 1: store the stage update
   int max_blocks;     // 0: fill the device once
@@ -46,6 +47,20 @@ struct VjpArgs {
   int flux;           // numerical flux: 0 Rusanov, 1 Roe
 };
 
+// Viscous (BR1) kernels: grad_kernel writes Z = grad U (15 state-layout variables,
+// index 5 k + v) to out; visc_kernel reads U and Z and writes the viscous residual part
+// Rv (5 variables) to out.  FP64 and FP32 (S = T = the mode's state type).
+struct ViscArgs {
+  const void* u;
+  const void* z;
+  void* out;
+  int max_blocks;
+  MeshView mesh;
+  const void* tab;    // the stage kernel's operand tables (16x16x4 layout)
+  double gamma, mu, prandtl;
+  double far[5];      // farfield conserved state
+};
+
 struct RefView {
   const double* qx;   // [N_q][3]
   const double* qw;   // [N_q]
@@ -55,6 +70,8 @@ struct RefView {
 };
 
 hipError_t launch_stage(int p, int prec, const StageArgs& a, hipStream_t stream);
+hipError_t launch_grad(int p, int prec, const ViscArgs& a, hipStream_t stream);
+hipError_t launch_visc(int p, int prec, const ViscArgs& a, hipStream_t stream);
 // Build the operand companion (q, c0) of an fp64 state for the mixed modes.
 hipError_t launch_pack(int p, int prec, const MeshView& m, const void* u, void* q, float* c0, hipStream_t s);
 // Bytes of one operand companion (q and c0) for the mixed modes.

@@ -36,58 +36,10 @@
 
 #include "dg_kernels.hpp"
 #include "dg_launch.hpp"
+#include "dg_tile.hpp"
 
 namespace tetdg {
 
-// Per-lane offsets (bytes, relative to the state base) of the coefficient planes a
-// lane reads for its MFMA B operands: with KW = 1 lane group g holds mode 4 s + g of
-// k-step s; with KW = 8 it holds modes 32 s + 8 g + m.  Modes past N_p (and mode 0 in
-// the mixed modes, whose mean is added separately) are clamped to a valid plane and
-// zeroed after the load, so every load is unconditional.
-template <class Pr, int NP, int KS>
-struct OperandMap {
-  static constexpr int NV = Pr::KW == 1 ? KS : 8 * KS;  // loads per variable
-  uint32_t off[NV];                                     // mode offset within a variable, bytes
-  bool keep[NV];
-  __device__ void init(int g, uint32_t quad_bytes) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      const int mode = Pr::KW == 1 ? 4 * i + g : 32 * (i / 8) + 8 * g + (i % 8);
-      const int mc = mode < NP ? mode : NP - 1;
-      keep[i] = mode < NP && !(Pr::mixed && mode == 0);
-      off[i] = (uint32_t)(mc >> 2) * quad_bytes + (uint32_t)(mc & 3) * sizeof(typename Pr::S);
-    }
-  }
-};
-
-template <class Pr, int NP, int KS>
-__device__ __forceinline__ void load_operands(const char* __restrict__ base, uint32_t var_bytes, uint32_t elem_off,
-                                              const OperandMap<Pr, NP, KS>& om, typename Pr::Op (&b)[5][KS]) {
-  using S = typename Pr::S;
-#pragma unroll
-  for (int v = 0; v < 5; ++v) {
-    const char* vb = base + (size_t)v * var_bytes;
-    if constexpr (Pr::KW == 1) {
-#pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        const S x = *reinterpret_cast<const S*>(vb + om.off[s] + elem_off);
-        b[v][s] = om.keep[s] ? typename Pr::Op(x) : typename Pr::Op(0);
-      }
-    } else {
-#pragma unroll
-      for (int s = 0; s < KS; ++s)
-#pragma unroll
-        for (int m = 0; m < 8; ++m) {
-          const int i = 8 * s + m;
-          const double x = double(*reinterpret_cast<const S*>(vb + om.off[i] + elem_off));
-          b[v][s][m] = (typename Pr::E1)(om.keep[i] ? float(x) : 0.0f);
-        }
-    }
-  }
-}
-
-// Two workgroups per CU (two waves per SIMD, at most 256 registers per lane) where the
-// live state fits; fp64 and P4 keep one (their tables and operands need the registers).
 // Packed pair of operand-precision values (KW = 8 modes); a placeholder otherwise.
 template <class Pr, bool = (Pr::KW == 8)>
 struct LiftPair {
@@ -99,33 +51,6 @@ struct LiftPair<Pr, true> {
   using E1 = typename Pr::E1;
   typedef E1 type __attribute__((ext_vector_type(2)));
 };
-
-// Projection / lift MFMA for one mode tile: the 4x4x1 block form for the short last
-// tile of the fp32 path (see kTail4; fp64 handles that tile with tail_fma), else the
-// precision's 16x16 instruction.
-template <class Pr, bool kTail4>
-__device__ __forceinline__ typename Pr::Acc mfma_tile(bool last, typename Pr::Op a, typename Pr::Op b,
-                                                      typename Pr::Acc c) {
-  if constexpr (kTail4 && !Pr::f64) {
-    if (last) return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
-  }
-  return Pr::mfma(a, b, c);
-}
-
-// FP64 short last tile: acc[v][r] += A[r] y[v] for the tile's modes r = 0..3, with the
-// four table values of this lane group's point read once (a broadcast within the group).
-template <class Pr>
-__device__ __forceinline__ void tail_fma(const typename Pr::Op* __restrict__ t, const typename Pr::T (&y)[5],
-                                         typename Pr::Acc (&acc)[5]) {
-  const double a0 = t[0], a1 = t[1], a2 = t[2], a3 = t[3];
-#pragma unroll
-  for (int v = 0; v < 5; ++v) {
-    acc[v][0] = __builtin_fma(a0, y[v], acc[v][0]);
-    acc[v][1] = __builtin_fma(a1, y[v], acc[v][1]);
-    acc[v][2] = __builtin_fma(a2, y[v], acc[v][2]);
-    acc[v][3] = __builtin_fma(a3, y[v], acc[v][3]);
-  }
-}
 
 template <int P, class Pr>
 constexpr int stage_min_blocks() {
@@ -511,13 +436,29 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
     // State values of mode tile mt (mode = 16 mt + drow(g, j)): with the fp32 accumulator
     // layout they form one mode quad per lane (one vector access); with the fp64 layout
     // they sit at position g of four quads.  Padding modes of the last quad are written 0.
-    double uin[5][4], u0v[5][4];
+    double uin[5][4], u0v[5][4], radd[5][4];
     auto load_tile = [&](int mt) {
 #pragma unroll
       for (int v = 0; v < 5; ++v)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) uin[v][j] = u0v[v][j] = 0.0;
-      if (!a.rk || !live) return;
+        for (int j = 0; j < 4; ++j) uin[v][j] = u0v[v][j] = radd[v][j] = 0.0;
+      if (!live) return;
+      if constexpr (!Pr::mixed) {
+        // an added residual part (the viscous terms) in the state's layout and precision
+        if (a.r_add) {
+          const char* rb = reinterpret_cast<const char*>(a.r_add);
+#pragma unroll
+          for (int v = 0; v < 5; ++v)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const int mode = 16 * mt + drow_of<Pr>(g, j);
+              if ((mode >> 2) < NPQ)
+                radd[v][j] = double(*reinterpret_cast<const S*>(rb + (size_t)v * var_bytes + (uint32_t)(mode >> 2) * quad_bytes +
+                                                                 ((size_t)e * 4 + (mode & 3)) * sizeof(S)));
+            }
+        }
+      }
+      if (!a.rk) return;
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         const size_t vo = (size_t)v * var_bytes + eoff;
@@ -605,6 +546,7 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
           double r = double(acc[mt][v][j]);
           if constexpr (Pr::mixed) r += mean[j];
           r *= ivol;
+          r += radd[v][j];
           const double out = a.rk ? a.alpha * u0v[v][j] + (1.0 - a.alpha) * (uin[v][j] + dt * r) : r;
           o[j] = mode < NP ? out : 0.0;
         }

@@ -92,6 +92,10 @@ class Solver:
         """'rusanov' (default) or 'roe'."""
         check(lib.tdg_set_flux(self._ctx, {"rusanov": 0, "roe": 1}[flux]), self._ctx, "tdg_set_flux")
 
+    def set_viscosity(self, mu: float, prandtl: float = 0.72) -> None:
+        """Navier-Stokes terms (BR1) with constant viscosity; call before upload()."""
+        check(lib.tdg_set_viscosity(self._ctx, float(mu), float(prandtl)), self._ctx, "tdg_set_viscosity")
+
     def set_farfield(self, prim) -> None:
         arr = np.ascontiguousarray(prim, dtype=np.float64)
         check(lib.tdg_set_farfield(self._ctx, arr.ctypes.data), self._ctx)

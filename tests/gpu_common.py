@@ -28,18 +28,21 @@ def make_mesh(kind: str):
     raise ValueError(kind)
 
 
-def solver(p, prec, mesh, renumber="hilbert", farfield=None):
+def solver(p, prec, mesh, renumber="hilbert", farfield=None, mu=0.0, prandtl=0.72):
     from paper_2209_01877_amd import Solver
 
     s = Solver(p, prec)
+    if mu > 0.0:
+        s.set_viscosity(mu, prandtl)
     s.upload(mesh, renumber=renumber)
     if farfield is not None:
         s.set_farfield(farfield)
     return s
 
 
-def oracle(p, mesh, farfield=(1.0, 0.5 * np.sqrt(1.4), 0.0, 0.0, 1.0)):
-    return DG(p, mesh.elem_vid, mesh.elem_xyz, mesh.bface_vid, mesh.bface_tag, farfield_prim=farfield)
+def oracle(p, mesh, farfield=(1.0, 0.5 * np.sqrt(1.4), 0.0, 0.0, 1.0), mu=0.0, prandtl=0.72):
+    return DG(p, mesh.elem_vid, mesh.elem_xyz, mesh.bface_vid, mesh.bface_tag, farfield_prim=farfield, mu=mu,
+              prandtl=prandtl)
 
 
 def random_state(dg, seed=7, scale=0.01):

@@ -126,6 +126,20 @@ def test_mesh_errors():
     _lib.lib.tdg_destroy(ctx)
 
 
+def test_viscosity_arguments():
+    ctx = _ctx()
+    assert _lib.lib.tdg_set_viscosity(ctx, -1.0, 0.72) == -1
+    assert _lib.lib.tdg_set_viscosity(ctx, 0.01, 0.0) == -1
+    assert _lib.lib.tdg_set_viscosity(ctx, 0.01, 0.72) == 0
+    assert _upload(ctx, kuhn_cube(3)) == 0
+    assert _lib.lib.tdg_set_viscosity(ctx, 0.02, 0.72) == -3  # after the upload
+    _lib.lib.tdg_destroy(ctx)
+    ctx = _ctx(prec=2)
+    assert _lib.lib.tdg_set_viscosity(ctx, 0.01, 0.72) == -5  # mixed modes
+    assert _lib.lib.tdg_set_viscosity(ctx, 0.0, 0.72) == 0
+    _lib.lib.tdg_destroy(ctx)
+
+
 def test_mesh_size_limits():
     """An empty mesh and an element count past the kernels' 32-bit element indexing are
     rejected before any array is read."""
