@@ -181,6 +181,38 @@ def run_p4(args):
     return out
 
 
+def run_navier_stokes(args):
+    """Viscous (BR1) form: P3 vortex on 48^3 x 6 with mu = 1e-3, FP64 and FP32: GDOF/s per
+    SSP-RK3 stage with the viscous terms, beside the same workload without them."""
+    from paper_2209_01877_amd import Solver
+
+    mesh = kuhn_cube(48, length=10.0, shuffle_seed=2209, vid_seed=2210)
+    p = 3
+    dt = 0.2 * 0.41 * (10.0 / 48) / ((2 * p + 1) * 3.1)
+    vortex = lambda x: fields.isentropic_vortex(x, length=10.0, beta=5.0, mach=0.5)  # noqa: E731
+    out = {}
+    for prec in ["fp64", "fp32"]:
+        row = {}
+        for mu in (1e-3, 0.0):
+            s = Solver(p, prec)
+            if mu > 0.0:
+                s.set_viscosity(mu, 0.72)
+            s.upload(mesh, renumber=args.renumber)
+            U = s.project_fn(vortex)
+            work = s.new_work()
+            s.rk_step(U, dt, 1, work)
+            steps = max(2, args.steps // 4)
+            t = timed(lambda: s.rk_step(U, dt, steps, work), 1, 0)
+            s.sync()
+            key = "navier_stokes" if mu > 0.0 else "euler"
+            row[key + "_gdof_per_s_per_stage"] = mesh.n_elem * s.n_modes * 5 * 3 * steps / t / 1e9
+            del s, U, work
+            torch.cuda.empty_cache()
+        out[prec] = row
+    out["workload"] = f"isentropic vortex, P3, 48^3 x 6 ({mesh.n_elem} tets), mu = 1e-3, Pr = 0.72"
+    return out
+
+
 def run_adjoint(args):
     """Differentiation form: P2 on the jittered 40^3 x 6 cube; time of the residual VJP over
     the time of the residual (fp64 and fp32)."""
@@ -304,6 +336,7 @@ def main():
     if not args.no_extra:
         line["p4_precision_form"] = run_p4(args)
         line["adjoint"] = run_adjoint(args)
+        line["navier_stokes"] = run_navier_stokes(args)
         line["adjoint_over_forward_fp64"] = line["adjoint"]["fp64"]["adjoint_over_forward"]
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args.p, args.cpu_n, args.cpu_steps)

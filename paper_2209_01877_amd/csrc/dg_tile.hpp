@@ -29,12 +29,12 @@ struct OperandMap {
   }
 };
 
-template <class Pr, int NP, int KS>
+template <class Pr, int NP, int KS, int NV = 5>
 __device__ __forceinline__ void load_operands(const char* __restrict__ base, uint32_t var_bytes, uint32_t elem_off,
-                                              const OperandMap<Pr, NP, KS>& om, typename Pr::Op (&b)[5][KS]) {
+                                              const OperandMap<Pr, NP, KS>& om, typename Pr::Op (&b)[NV][KS]) {
   using S = typename Pr::S;
 #pragma unroll
-  for (int v = 0; v < 5; ++v) {
+  for (int v = 0; v < NV; ++v) {
     const char* vb = base + (size_t)v * var_bytes;
     if constexpr (Pr::KW == 1) {
 #pragma unroll

@@ -132,6 +132,42 @@ __device__ __forceinline__ void project_point(const typename Pr::Op* __restrict_
     }
 }
 
+// One direction dd of one point j of the projection: acc[mt][v] += P(mt, qt, 4 dd + j) y[v].
+template <class Pr, int MT, bool kTail4, class L>
+__device__ __forceinline__ void project_dir(const typename Pr::Op* __restrict__ tab, int qt, int j, int dd, int lane,
+                                            int g, typename Pr::T (&y)[5], typename Pr::Acc (&acc)[MT][5]) {
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    if constexpr (kTail4 && Pr::f64) {
+      if (mt == MT - 1) {
+        tail_fma<Pr>(tab + L::proj(mt, qt, 4 * dd + j) * 64 + 16 * g, y, acc[mt]);
+        continue;
+      }
+    }
+    const typename Pr::Op av = tab[L::proj(mt, qt, 4 * dd + j) * 64 + lane];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) acc[mt][v] = mfma_tile<Pr, kTail4>(mt == MT - 1, av, y[v], acc[mt][v]);
+  }
+}
+
+// One point lk of the lift of a face tile: acc[mt][v] += L(mt, f, ft, lk) h[v].
+template <class Pr, int MT, bool kTail4, class L>
+__device__ __forceinline__ void lift_point(const typename Pr::Op* __restrict__ tab, int f, int ft, int lk, int lane,
+                                           int g, typename Pr::T (&h)[5], typename Pr::Acc (&acc)[MT][5]) {
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    if constexpr (kTail4 && Pr::f64) {
+      if (mt == MT - 1) {
+        tail_fma<Pr>(tab + L::lift(mt, f, ft, lk) * 64 + 16 * g, h, acc[mt]);
+        continue;
+      }
+    }
+    const typename Pr::Op av = tab[L::lift(mt, f, ft, lk) * 64 + lane];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) acc[mt][v] = mfma_tile<Pr, kTail4>(mt == MT - 1, av, h[v], acc[mt][v]);
+  }
+}
+
 // Accumulate the lift of one face tile: acc[mt][v] += L(mt, f, ft, lk) fh[v][lk].
 template <class Pr, int MT, bool kTail4, class L>
 __device__ __forceinline__ void lift_face(const typename Pr::Op* __restrict__ tab, int f, int ft, int lane, int g,
@@ -337,23 +373,30 @@ __global__ __launch_bounds__(256) void visc_kernel(ViscArgs a) {
 #pragma unroll
       for (int v = 0; v < 5; ++v) acc[mt][v] = Acc{0, 0, 0, 0};
 
-    // values of U (w = 0) and Z_k (w = 1 + k) of element el at the points of a tile,
-    // by table t(s): out[w][v] (interpolation / trace contractions)
-    auto gather = [&](uint32_t el_off, auto&& table, const bool* mask, Acc (&out)[4][5]) {
+    // values of U (w = 0) and Z_k (w = 1 + k) of element el at the points of a tile, by
+    // table t(s), accumulated into out[w][v] (interpolation / trace contractions; with a
+    // mask, only the columns where it holds contribute)
+    auto gather = [&](uint32_t el_off, auto&& table, bool use, Acc (&out)[4][5]) {
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
-        Op b[5][KS];
         const char* src = w == 0 ? ubase : zbase + (size_t)(5 * (w - 1)) * var_bytes;
-        load_operands<Pr, NP, KS>(src, var_bytes, el_off, om, b);
 #pragma unroll
-        for (int v = 0; v < 5; ++v) out[w][v] = Acc{0, 0, 0, 0};
+        for (int v = 0; v < 5; ++v) {
+          Op b[1][KS];
+          load_operands<Pr, NP, KS, 1>(src + (size_t)v * var_bytes, var_bytes, el_off, om, b);
 #pragma unroll
-        for (int s = 0; s < KS; ++s) {
-          const Op av = tab[table(s) * 64 + lane];
-#pragma unroll
-          for (int v = 0; v < 5; ++v) out[w][v] = Pr::mfma(av, (mask == nullptr || *mask) ? b[v][s] : Op(0), out[w][v]);
+          for (int s = 0; s < KS; ++s) {
+            const Op av = tab[table(s) * 64 + lane];
+            out[w][v] = Pr::mfma(av, use ? b[0][s] : Op(0), out[w][v]);
+          }
         }
       }
+    };
+    auto zero = [&](Acc (&out)[4][5]) {
+#pragma unroll
+      for (int w = 0; w < 4; ++w)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) out[w][v] = Acc{0, 0, 0, 0};
     };
     auto point = [&](const Acc (&vals)[4][5], int j, T (&U)[5], T (&Z)[3][5]) {
 #pragma unroll
@@ -368,26 +411,22 @@ __global__ __launch_bounds__(256) void visc_kernel(ViscArgs a) {
 #pragma unroll 1
     for (int qt = 0; qt < QT; ++qt) {
       Acc vals[4][5];
-      gather(eoff, [&](int s) { return L::interp(qt, s); }, nullptr, vals);
+      zero(vals);
+      gather(eoff, [&](int s) { return L::interp(qt, s); }, true, vals);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int q = 16 * qt + drow(Pr::f64, g, j);
-        T y[3][5];
-        if (q < NQ) {
-          T U[5], Z[3][5], Fv[3][5];
-          point(vals, j, U, Z);
-          visc_flux<T>(U, Z, gm1, mu, kappa, Fv);
+        T U[5], Z[3][5], Fv[3][5];
+        point(vals, j, U, Z);
+        visc_flux<T>(U, Z, gm1, mu, kappa, Fv);
 #pragma unroll
-          for (int dd = 0; dd < 3; ++dd)
+        for (int dd = 0; dd < 3; ++dd) {
+          T y[5];
 #pragma unroll
-            for (int v = 0; v < 5; ++v) y[dd][v] = Mt[3 * dd] * Fv[0][v] + Mt[3 * dd + 1] * Fv[1][v] + Mt[3 * dd + 2] * Fv[2][v];
-        } else {
-#pragma unroll
-          for (int dd = 0; dd < 3; ++dd)
-#pragma unroll
-            for (int v = 0; v < 5; ++v) y[dd][v] = T(0);
+          for (int v = 0; v < 5; ++v)
+            y[v] = q < NQ ? Mt[3 * dd] * Fv[0][v] + Mt[3 * dd + 1] * Fv[1][v] + Mt[3 * dd + 2] * Fv[2][v] : T(0);
+          project_dir<Pr, MT, kTail4, L>(tab, qt, j, dd, lane, g, y, acc);
         }
-        project_point<Pr, MT, kTail4, L>(tab, qt, j, lane, g, y, acc);
       }
     }
 
@@ -403,8 +442,8 @@ __global__ __launch_bounds__(256) void visc_kernel(ViscArgs a) {
         // own half (and, on a boundary face, the ghost half with Z+ = Z-)
         {
           Acc vals[4][5];
-          gather(eoff, [&](int s) { return L::trace(f, ft, s); }, nullptr, vals);
-          T fh[5][4];
+          zero(vals);
+          gather(eoff, [&](int s) { return L::trace(f, ft, s); }, true, vals);
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             const int q = 16 * ft + drow(Pr::f64, g, j);
@@ -421,31 +460,40 @@ __global__ __launch_bounds__(256) void visc_kernel(ViscArgs a) {
               for (int v = 0; v < 5; ++v) h[v] += Fv[0][v] * N[0] + Fv[1][v] * N[1] + Fv[2][v] * N[2];
             }
 #pragma unroll
-            for (int v = 0; v < 5; ++v) fh[v][j] = q < NF ? T(0.5) * h[v] : T(0);
+            for (int v = 0; v < 5; ++v) h[v] = q < NF ? T(0.5) * h[v] : T(0);
+            lift_point<Pr, MT, kTail4, L>(tab, f, ft, j, lane, g, h, acc);
           }
-          lift_face<Pr, MT, kTail4, L>(tab, f, ft, lane, g, fh, acc);
         }
         // neighbour half: its traces through its own face table f+ (masked per column)
         if (__any(nbf >= 0)) {
           const uint32_t noff = (uint32_t)(nbf >= 0 ? nbf : e) * 4 * sizeof(S);
           Acc vals[4][5];
+          zero(vals);
+          // each operand is read once and applied through every face table present in the
+          // tile, masked to the columns whose neighbour uses that table
+          bool mine[4], any[4];
 #pragma unroll
-          for (int w = 0; w < 4; ++w)
-#pragma unroll
-            for (int v = 0; v < 5; ++v) vals[w][v] = Acc{0, 0, 0, 0};
-#pragma unroll 1
           for (int c = 0; c < 4; ++c) {
-            const bool mine = nbf >= 0 && fpl == c;
-            if (__any(mine)) {
-              Acc part[4][5];
-              gather(noff, [&](int s) { return L::trace(c, ft, s); }, &mine, part);
+            mine[c] = nbf >= 0 && fpl == c;
+            any[c] = __any(mine[c]);
+          }
 #pragma unroll
-              for (int w = 0; w < 4; ++w)
+          for (int w = 0; w < 4; ++w) {
+            const char* src = w == 0 ? ubase : zbase + (size_t)(5 * (w - 1)) * var_bytes;
 #pragma unroll
-                for (int v = 0; v < 5; ++v) vals[w][v] += part[w][v];
+            for (int v = 0; v < 5; ++v) {
+              Op b[1][KS];
+              load_operands<Pr, NP, KS, 1>(src + (size_t)v * var_bytes, var_bytes, noff, om, b);
+#pragma unroll
+              for (int c = 0; c < 4; ++c) {
+                if (any[c]) {
+#pragma unroll
+                  for (int s = 0; s < KS; ++s)
+                    vals[w][v] = Pr::mfma(tab[L::trace(c, ft, s) * 64 + lane], mine[c] ? b[0][s] : Op(0), vals[w][v]);
+                }
+              }
             }
           }
-          T fh[5][4];
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             const int q = 16 * ft + drow(Pr::f64, g, j);
@@ -455,12 +503,10 @@ __global__ __launch_bounds__(256) void visc_kernel(ViscArgs a) {
               point(vals, j, U, Z);
               visc_flux<T>(U, Z, gm1, mu, kappa, Fv);
 #pragma unroll
-              for (int v = 0; v < 5; ++v) h[v] = Fv[0][v] * N[0] + Fv[1][v] * N[1] + Fv[2][v] * N[2];
+              for (int v = 0; v < 5; ++v) h[v] = T(0.5) * (Fv[0][v] * N[0] + Fv[1][v] * N[1] + Fv[2][v] * N[2]);
             }
-#pragma unroll
-            for (int v = 0; v < 5; ++v) fh[v][j] = T(0.5) * h[v];
+            lift_point<Pr, MT, kTail4, L>(tab, f, ft, j, lane, g, h, acc);
           }
-          lift_face<Pr, MT, kTail4, L>(tab, f, ft, lane, g, fh, acc);
         }
       }
     }
