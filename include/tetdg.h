@@ -247,6 +247,15 @@ int tdg_stable_dt(tdg_ctx* ctx, const void* U, double cfl, double* dt, void* hip
 /* Synchronise the stream; map a pending asynchronous HIP error to TDG_ERR_HIP. */
 int tdg_sync_check(tdg_ctx* ctx, void* hip_stream);
 
+/* Streaming probe: the practical DRAM bandwidth that the roofline model of Sec. IV.A bounds
+ * a memory-bound kernel by, measured with 16-byte non-temporal accesses over caller device
+ * buffers (grid-strided, 512-thread workgroups).  kind 0 copies src to dst, kind 1 only reads
+ * src (dst: at least 16 bytes, whose first 16 may be overwritten), kind 2 zero-fills dst.
+ * bytes: a positive multiple of 16; src and dst 16-byte aligned and not overlapping (src may
+ * be NULL for kind 2).  Asynchronous on hip_stream; no context, no allocation.  Errors:
+ * TDG_ERR_INVALID_ARG (checked before any device call), TDG_ERR_HIP (launch failure). */
+int tdg_stream_probe(int kind, const void* src, void* dst, size_t bytes, void* hip_stream);
+
 /* ------------------------------------------------------------------ host-only checks */
 
 /* Reference tables computed by this library, no GPU needed.  which:

@@ -56,6 +56,7 @@ _SIGS = {
     "tdg_stable_dt": (_i, [_p, _p, _d, _p, _p]),
     "tdg_sync_check": (_i, [_p, _p]),
     "tdg_debug_tables": (_i, [_i, _i, _p, _sz, ctypes.POINTER(_sz)]),
+    "tdg_stream_probe": (_i, [_i, _p, _p, _sz, _p]),
 }
 
 for _name, (_res, _args) in _SIGS.items():

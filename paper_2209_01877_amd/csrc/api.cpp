@@ -884,6 +884,12 @@ int tdg_sync_check(tdg_ctx* c, void* s) {
   return e == hipSuccess ? TDG_OK : hip_fail(c, e, "stream synchronize");
 }
 
+int tdg_stream_probe(int kind, const void* src, void* dst, size_t bytes, void* s) {
+  if (kind < 0 || kind > 2 || bytes == 0 || bytes % 16 != 0 || !dst || (kind != 2 && !src)) return TDG_ERR_INVALID_ARG;
+  if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16 != 0) return TDG_ERR_INVALID_ARG;
+  return launch_stream_probe(kind, src, dst, bytes, (hipStream_t)s) == hipSuccess ? TDG_OK : TDG_ERR_HIP;
+}
+
 int tdg_debug_tables(int order_p, int which, double* out, size_t cap, size_t* need) {
   if (order_p < 1 || order_p > 4 || which < 0 || which > 6 || !need) return TDG_ERR_INVALID_ARG;
   RefElem R;

@@ -86,6 +86,7 @@ hipError_t launch_check_state(int p, int prec, const MeshView& m, const RefView&
                               int64_t* n_bad, hipStream_t s);
 hipError_t launch_local_dt(int p, int prec, const MeshView& m, double gamma, double cfl, const void* u, double* dt,
                            hipStream_t s);
+hipError_t launch_stream_probe(int kind, const void* src, void* dst, size_t bytes, hipStream_t s);
 hipError_t launch_project(int p, int prec, const MeshView& m, const RefView& r, double gamma, const double* prim,
                           void* internal, hipStream_t s);
 

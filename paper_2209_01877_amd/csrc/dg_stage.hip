@@ -558,7 +558,8 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
             s4_t x;
 #pragma unroll
             for (int j = 0; j < 4; ++j) x[j] = S(o[j]);
-            *reinterpret_cast<s4_t*>(obase + vo + (size_t)qd * quad_bytes) = x;
+            // streamed out: not read again within this launch
+            __builtin_nontemporal_store(x, reinterpret_cast<s4_t*>(obase + vo + (size_t)qd * quad_bytes));
           }
         } else {
 #pragma unroll

@@ -159,6 +159,27 @@ __global__ void fill_u64_kernel(unsigned long long* p, unsigned long long v) { *
 inline int np_of(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+
+// Streaming probe: 16-byte non-temporal accesses over caller buffers, grid-strided.
+// kind 0 copies src to dst, kind 1 reads src (its XOR reduction reaches dst[0] only for one
+// bit pattern, so the loads stay live), kind 2 zero-fills dst.
+typedef unsigned stream_u4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(512) void stream_kernel(int kind, const stream_u4* __restrict__ src,
+                                                     stream_u4* __restrict__ dst, int64_t n16) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (kind == 0) {
+    for (; i < n16; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+  } else if (kind == 1) {
+    stream_u4 x = {0u, 0u, 0u, 0u};
+    for (; i < n16; i += stride) x ^= __builtin_nontemporal_load(src + i);
+    if (x[0] == 0x9e3779b9u && x[1] == 0x7f4a7c15u && x[2] == 0xf39cc060u && x[3] == 0x5ced1e02u) dst[0] = x;
+  } else {
+    const stream_u4 z = {0u, 0u, 0u, 0u};
+    for (; i < n16; i += stride) __builtin_nontemporal_store(z, dst + i);
+  }
+}
+
 }  // namespace
 
 hipError_t launch_set_state(int p, int prec, const MeshView& m, const double* user, void* internal, hipStream_t s) {
@@ -255,6 +276,15 @@ hipError_t launch_project(int p, int prec, const MeshView& m, const RefView& r, 
   else
     hipLaunchKernelGGL(project_kernel<double>, dim3(nblocks(m.epad * np, 256)), dim3(256), 0, s, m, np, nq, r, gamma,
                        prim, (double*)internal);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_probe(int kind, const void* src, void* dst, size_t bytes, hipStream_t s) {
+  const int64_t n16 = (int64_t)(bytes / 16);
+  int64_t nb = (n16 + 511) / 512;
+  if (nb > 65536) nb = 65536;  // grid-strided beyond 32 M threads
+  hipLaunchKernelGGL(stream_kernel, dim3((unsigned)nb), dim3(512), 0, s, kind, (const stream_u4*)src, (stream_u4*)dst,
+                     n16);
   return hipGetLastError();
 }
 
