@@ -63,9 +63,17 @@ __device__ __forceinline__ void visc_flux(const T U[5], const T Z[3][5], T gm1, 
   }
 }
 
+// FP32 up to P3 fits two waves per SIMD without spilling; FP64 and P4 take one.
+template <int P, class Pr>
+constexpr int visc_min_blocks() {
+  return (!Pr::f64 && P <= 3) ? 2 : 1;
+}
+
 template <int P, class Pr>
 constexpr bool visc_lds() {
-  return sizeof(typename Pr::Op) * Layout<P, 1>::n_slots * 64 <= 96 * 1024;
+  // at most 96 KB, and within the LDS share of each resident workgroup (160 KB per CU)
+  constexpr size_t share = 160 * 1024 / visc_min_blocks<P, Pr>();
+  return sizeof(typename Pr::Op) * Layout<P, 1>::n_slots * 64 <= (share < 96 * 1024 ? share : 96 * 1024);
 }
 
 // Shared prologue: tables (LDS when they fit), lane coordinates, the XCD-local sweep.
@@ -239,7 +247,7 @@ __device__ __forceinline__ void store_tile(char* __restrict__ obase, uint32_t va
 
 // BR1 lifting: Z_k = (-int U d_k phi + sum_f int (U- + U+)/2 N_k phi) / |K|.
 template <int P, class Pr>
-__global__ __launch_bounds__(256) void grad_kernel(ViscArgs a) {
+__global__ __launch_bounds__(256, (visc_min_blocks<P, Pr>())) void grad_kernel(ViscArgs a) {
   TDG_VISC_PROLOGUE
   char* __restrict__ zout = reinterpret_cast<char*>(a.out);
   for (int64_t grp = g_begin + wave_x; grp < g_end; grp += waves_x) {
@@ -349,7 +357,7 @@ __global__ __launch_bounds__(256) void grad_kernel(ViscArgs a) {
 
 // Viscous residual Rv = -(Vv - Sv) / |K| from U and Z.
 template <int P, class Pr>
-__global__ __launch_bounds__(256) void visc_kernel(ViscArgs a) {
+__global__ __launch_bounds__(256, (visc_min_blocks<P, Pr>())) void visc_kernel(ViscArgs a) {
   TDG_VISC_PROLOGUE
   const char* __restrict__ zbase = reinterpret_cast<const char*>(a.z);
   char* __restrict__ obase = reinterpret_cast<char*>(a.out);
@@ -377,6 +385,9 @@ __global__ __launch_bounds__(256) void visc_kernel(ViscArgs a) {
     // table t(s), accumulated into out[w][v] (interpolation / trace contractions; with a
     // mask, only the columns where it holds contribute)
     auto gather = [&](uint32_t el_off, auto&& table, bool use, Acc (&out)[4][5]) {
+      // the element's own operands are the same in every tile: an opaque offset keeps their
+      // loads inside the loop (hoisted out, 20 variables x KS operands stay live and spill)
+      asm volatile("" : "+v"(el_off));
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
         const char* src = w == 0 ? ubase : zbase + (size_t)(5 * (w - 1)) * var_bytes;
