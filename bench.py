@@ -304,7 +304,8 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=28)
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the P4 and adjoint workloads")
+    ap.add_argument("--no-extra", action="store_true", help="skip the P4, adjoint and Navier-Stokes workloads")
+    ap.add_argument("--extras", default="p4,adjoint,navier_stokes", help="which of those to run")
     ap.add_argument("--copy-calibration", action="store_true", help="run a 1 GiB device copy first")
     args = ap.parse_args()
     args.precisions = args.precisions.split(",")
@@ -371,11 +372,14 @@ def main():
     line["stream_ceiling"] = ceiling
     if "fp32" in res and head != "fp32":
         line["speedup_vs_fp32"] = r["gdof_per_s_per_stage"] / res["fp32"]["gdof_per_s_per_stage"]
-    if not args.no_extra:
+    extras = [] if args.no_extra else args.extras.split(",")
+    if "p4" in extras:
         line["p4_precision_form"] = run_p4(args)
+    if "adjoint" in extras:
         line["adjoint"] = run_adjoint(args)
-        line["navier_stokes"] = run_navier_stokes(args)
         line["adjoint_over_forward_fp64"] = line["adjoint"]["fp64"]["adjoint_over_forward"]
+    if "navier_stokes" in extras:
+        line["navier_stokes"] = run_navier_stokes(args)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args.p, args.cpu_n, args.cpu_steps)
     print(json.dumps(line), flush=True)

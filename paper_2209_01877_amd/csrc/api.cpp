@@ -39,7 +39,7 @@ struct tdg_ctx {
   int flux = TDG_FLUX_RUSANOV;
   // viscous (Navier-Stokes, BR1) terms: off when mu == 0; scratch Z (3 states) and Rv
   double mu = 0.0, prandtl = 0.72;
-  size_t off_z = 0, off_rv = 0;
+  size_t off_z = 0, off_rv = 0, off_hb = 0;
 };
 
 namespace {
@@ -466,6 +466,9 @@ int tdg_mesh_upload(tdg_ctx* c, int64_t n_elem, const int64_t* elem_vid, const d
       const size_t sb = (size_t)5 * ((c->ref.np + 3) / 4) * epad * 4 * (c->prec == TDG_FP32 ? 4 : 8);
       c->off_z = take(c->mu > 0.0 ? 3 * sb : 0);
       c->off_rv = take(c->mu > 0.0 ? sb : 0);
+      // own-half viscous face fluxes at the face points, 4 faces x 5 variables per element
+      const size_t hb = (size_t)epad * 4 * 5 * c->ref.fw.size() * (c->prec == TDG_FP32 ? 4 : 8);
+      c->off_hb = take(c->mu > 0.0 ? hb : 0);
     }
     c->total = off;
     c->has_mesh = true;
@@ -661,10 +664,13 @@ static hipError_t viscous_part(tdg_ctx* c, const void* U, StageArgs& a, hipStrea
   v.mu = c->mu;
   v.prandtl = c->prandtl;
   for (int k = 0; k < 5; ++k) v.far[k] = c->far[k];
+  v.hbuf = c->dev + c->off_hb;
   hipError_t e = launch_grad(c->p, c->prec, v, s);
   if (e != hipSuccess) return e;
   v.out = c->dev + c->off_rv;
   e = launch_visc(c->p, c->prec, v, s);
+  if (e != hipSuccess) return e;
+  e = launch_visc_nbr(c->p, c->prec, v, s);
   a.r_add = c->dev + c->off_rv;
   return e;
 }

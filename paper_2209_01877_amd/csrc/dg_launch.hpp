@@ -59,6 +59,7 @@ struct ViscArgs {
   const void* tab;    // the stage kernel's operand tables (16x16x4 layout)
   double gamma, mu, prandtl;
   double far[5];      // farfield conserved state
+  void* hbuf;         // own-half viscous face fluxes, [E_pad][4 faces][5][N_f] (state precision)
 };
 
 struct RefView {
@@ -72,6 +73,7 @@ struct RefView {
 hipError_t launch_stage(int p, int prec, const StageArgs& a, hipStream_t stream);
 hipError_t launch_grad(int p, int prec, const ViscArgs& a, hipStream_t stream);
 hipError_t launch_visc(int p, int prec, const ViscArgs& a, hipStream_t stream);
+hipError_t launch_visc_nbr(int p, int prec, const ViscArgs& a, hipStream_t stream);
 // Build the operand companion (q, c0) of an fp64 state for the mixed modes.
 hipError_t launch_pack(int p, int prec, const MeshView& m, const void* u, void* q, float* c0, hipStream_t s);
 // Bytes of one operand companion (q and c0) for the mixed modes.

@@ -7,15 +7,18 @@
 //   |K| Z_k,i = -sum_q w_q |det J| dphi_i/dx_k U(q) + sum_f sum_q w^f_q (U- + U+)/2 N_k phi_i
 //   Rv_i      = -(Vv_i - Sv_i) / |K|,   Vv_i = int_K F_v(U, Z) . grad phi_i,
 //               Sv_i = sum_f int_f (F_v(U-, Z-) + F_v(U+, Z+))/2 . n phi_i
-// with the inviscid ghost state as U+ on boundary faces and Z+ = Z- there.  Two kernels,
+// with the inviscid ghost state as U+ on boundary faces and Z+ = Z- there.  Three kernels,
 // each in the column-tile structure of the stage kernel (16 elements per wavefront, the
 // same MFMA operand tables):
-//   grad_kernel : Z for the three directions (stored as 15 state-layout variables 5 k + v)
-//   visc_kernel : Rv, read by the stage kernel's epilogue as an added residual.
-// Each element gathers its neighbours' U (and, for Rv, Z) and writes only its own
-// output: no atomics.  Since the BR1 interface flux is an average, the face term splits
-// into the element's own half and its neighbour's half, which are lifted one after the
-// other (the neighbour half through the neighbour's face table, selected per column).
+//   grad_kernel     : Z for the three directions (stored as 15 state-layout variables 5 k + v)
+//   visc_kernel     : the volume term and the element's own half of every face term of Rv;
+//                     the own half F_v(U-, Z-) . N / 2 at the face points is also stored
+//   visc_nbr_kernel : adds the neighbours' halves, read from that store, to Rv
+// Rv is read by the stage kernel's epilogue as an added residual.  Since the BR1 interface
+// flux is an average, the face term splits into two halves; the neighbour's half at our
+// face points is minus its own half at its face points (opposite normal, and two elements
+// sharing a face parametrise it identically), so it is computed once, by its owner.  Each
+// kernel writes only its own elements' outputs: no atomics.
 #include <hip/hip_runtime.h>
 
 #include "dg_kernels.hpp"
@@ -246,6 +249,12 @@ __device__ __forceinline__ void store_tile(char* __restrict__ obase, uint32_t va
 }
 
 // BR1 lifting: Z_k = (-int U d_k phi + sum_f int (U- + U+)/2 N_k phi) / |K|.
+// Both terms are linear in the rows of M = |det J| J^-1: the volume integrand's contravariant
+// components are M[d][k] U, and the face normal is N_f,k = sum_d M[d][k] n_f,d with the
+// reference face normals n_0 = (1, 1, 1), n_1 = -e_0, n_2 = -e_1, n_3 = -e_2.  So one
+// interpolation, one set of traces and three reference-direction sums
+//   D_d = sum_q w_q dphi/dxi_d U(q) - sum_f n_f,d int_f Uhat phi
+// serve all three directions: Z_k = -(sum_d M[d][k] D_d) / |K|.
 template <int P, class Pr>
 __global__ __launch_bounds__(256, (visc_min_blocks<P, Pr>())) void grad_kernel(ViscArgs a) {
   TDG_VISC_PROLOGUE
@@ -255,102 +264,112 @@ __global__ __launch_bounds__(256, (visc_min_blocks<P, Pr>())) void grad_kernel(V
     double Md[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) Md[i] = mv.M[i * epad + e];
-    T Mt[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) Mt[i] = T(Md[i]);
     const int fcode = mv.fcode[e];
     int nbr[4];
 #pragma unroll
     for (int f = 0; f < 4; ++f) nbr[f] = mv.nbr[f * epad + e];
     Op bc[5][KS];
     load_operands<Pr, NP, KS>(ubase, var_bytes, (uint32_t)e * 4 * sizeof(S), om, bc);
-    const double ivol = mv.inv_vol[e];
-#pragma unroll 1
-    for (int k = 0; k < 3; ++k) {
-      Acc acc[MT][5];
+    Acc acc[3][MT][5];  // D_d, d = reference direction
+#pragma unroll
+    for (int dd = 0; dd < 3; ++dd)
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int v = 0; v < 5; ++v) acc[mt][v] = Acc{0, 0, 0, 0};
-      // volume: "flux" U e_k, contravariant y_d = M[d][k] U
+        for (int v = 0; v < 5; ++v) acc[dd][mt][v] = Acc{0, 0, 0, 0};
+    // volume: U at the points, projected on the three reference gradients
 #pragma unroll 1
-      for (int qt = 0; qt < QT; ++qt) {
-        Acc d[5];
+    for (int qt = 0; qt < QT; ++qt) {
+      Acc d[5];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) d[v] = Acc{0, 0, 0, 0};
+      for (int v = 0; v < 5; ++v) d[v] = Acc{0, 0, 0, 0};
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const Op av = tab[L::interp(qt, s) * 64 + lane];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) d[v] = Pr::mfma(av, bc[v][s], d[v]);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int q = 16 * qt + drow(Pr::f64, g, j);
+        T y[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) y[v] = q < NQ ? T(d[v][j]) : T(0);
+#pragma unroll
+        for (int dd = 0; dd < 3; ++dd) project_dir<Pr, MT, kTail4, L>(tab, qt, j, dd, lane, g, y, acc[dd]);
+      }
+    }
+    // faces: Uhat = (U- + U+)/2 lifted once per face, into the directions where n_f,d != 0
+#pragma unroll 1
+    for (int f = 0; f < 4; ++f) {
+      T N[3];
+      face_normal<T>(f, Md, N);
+      const int nbf = f == 0 ? nbr[0] : f == 1 ? nbr[1] : f == 2 ? nbr[2] : nbr[3];
+      const int fpl = (fcode >> (2 * f)) & 3;
+      const int en = nbf >= 0 ? nbf : e;
+      Op bn[5][KS];
+      load_operands<Pr, NP, KS>(ubase, var_bytes, (uint32_t)en * 4 * sizeof(S), om, bn);
+#pragma unroll 1
+      for (int ft = 0; ft < FT; ++ft) {
+        Acc dm[5], dp[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) dm[v] = dp[v] = Acc{0, 0, 0, 0};
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
-          const Op av = tab[L::interp(qt, s) * 64 + lane];
+          const Op av = tab[L::trace(f, ft, s) * 64 + lane];
 #pragma unroll
-          for (int v = 0; v < 5; ++v) d[v] = Pr::mfma(av, bc[v][s], d[v]);
+          for (int v = 0; v < 5; ++v) dm[v] = Pr::mfma(av, bc[v][s], dm[v]);
         }
+#pragma unroll 1
+        for (int c = 0; c < 4; ++c) {
+          const bool mine = nbf >= 0 && fpl == c;
+          if (__any(mine)) {
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+              const Op av = tab[L::trace(c, ft, s) * 64 + lane];
+#pragma unroll
+              for (int v = 0; v < 5; ++v) dp[v] = Pr::mfma(av, mine ? bn[v][s] : Op(0), dp[v]);
+            }
+          }
+        }
+        // n_f,d Uhat: +Uhat for face 0 (all d), -Uhat for face f > 0 (d = f - 1)
+        const T sgn = f == 0 ? T(0.5) : T(-0.5);
+        T fh[5][4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int q = 16 * qt + drow(Pr::f64, g, j);
-          const T mk[3] = {k == 0 ? Mt[0] : k == 1 ? Mt[1] : Mt[2], k == 0 ? Mt[3] : k == 1 ? Mt[4] : Mt[5],
-                           k == 0 ? Mt[6] : k == 1 ? Mt[7] : Mt[8]};
-          T y[3][5];
+          const int q = 16 * ft + drow(Pr::f64, g, j);
+          T um[5], up[5];
 #pragma unroll
-          for (int dd = 0; dd < 3; ++dd)
+          for (int v = 0; v < 5; ++v) {
+            um[v] = T(dm[v][j]);
+            up[v] = T(dp[v][j]);
+          }
+          if (nbf < 0) ghost_state<T>(-nbf, um, N, far, up);
 #pragma unroll
-            for (int v = 0; v < 5; ++v) y[dd][v] = q < NQ ? mk[dd] * T(d[v][j]) : T(0);
-          project_point<Pr, MT, kTail4, L>(tab, qt, j, lane, g, y, acc);
+          for (int v = 0; v < 5; ++v) fh[v][j] = q < NF ? sgn * (um[v] + up[v]) : T(0);
         }
+#pragma unroll
+        for (int dd = 0; dd < 3; ++dd)
+          if (f == 0 || f == dd + 1) lift_face<Pr, MT, kTail4, L>(tab, f, ft, lane, g, fh, acc[dd]);
       }
-      // faces: (U- + U+)/2 N_k
-#pragma unroll 1
-      for (int f = 0; f < 4; ++f) {
-        T N[3];
-        face_normal<T>(f, Md, N);
-        const int nbf = f == 0 ? nbr[0] : f == 1 ? nbr[1] : f == 2 ? nbr[2] : nbr[3];
-        const int fpl = (fcode >> (2 * f)) & 3;
-        const int en = nbf >= 0 ? nbf : e;
-        Op bn[5][KS];
-        load_operands<Pr, NP, KS>(ubase, var_bytes, (uint32_t)en * 4 * sizeof(S), om, bn);
-        const T nk = k == 0 ? N[0] : k == 1 ? N[1] : N[2];
-#pragma unroll 1
-        for (int ft = 0; ft < FT; ++ft) {
-          Acc dm[5], dp[5];
+    }
+    // Z_k = -(sum_d M[d][k] D_d) / |K|
+    const double ivol = mv.inv_vol[e];
+    T Mt[9];
 #pragma unroll
-          for (int v = 0; v < 5; ++v) dm[v] = dp[v] = Acc{0, 0, 0, 0};
+    for (int i = 0; i < 9; ++i) Mt[i] = T(Md[i]);
 #pragma unroll
-          for (int s = 0; s < KS; ++s) {
-            const Op av = tab[L::trace(f, ft, s) * 64 + lane];
+    for (int k = 0; k < 3; ++k) {
+      Acc z[MT][5];
 #pragma unroll
-            for (int v = 0; v < 5; ++v) dm[v] = Pr::mfma(av, bc[v][s], dm[v]);
-          }
-#pragma unroll 1
-          for (int c = 0; c < 4; ++c) {
-            const bool mine = nbf >= 0 && fpl == c;
-            if (__any(mine)) {
+      for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-              for (int s = 0; s < KS; ++s) {
-                const Op av = tab[L::trace(c, ft, s) * 64 + lane];
+        for (int v = 0; v < 5; ++v)
 #pragma unroll
-                for (int v = 0; v < 5; ++v) dp[v] = Pr::mfma(av, mine ? bn[v][s] : Op(0), dp[v]);
-              }
-            }
-          }
-          T fh[5][4];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int q = 16 * ft + drow(Pr::f64, g, j);
-            T um[5], up[5];
-#pragma unroll
-            for (int v = 0; v < 5; ++v) {
-              um[v] = T(dm[v][j]);
-              up[v] = T(dp[v][j]);
-            }
-            if (nbf < 0) ghost_state<T>(-nbf, um, N, far, up);
-#pragma unroll
-            for (int v = 0; v < 5; ++v) fh[v][j] = q < NF ? T(0.5) * (um[v] + up[v]) * nk : T(0);
-          }
-          lift_face<Pr, MT, kTail4, L>(tab, f, ft, lane, g, fh, acc);
-        }
-      }
-      finish_tail<Pr, MT, kTail4>(g, acc);
-      // acc = V - S with V = int U d_k phi, S = int Uhat N_k phi: Z_k = -acc / |K|
-      if (e < mv.n_elem) store_tile<Pr, NP, MT>(zout + (size_t)(5 * k) * var_bytes, var_bytes, quad_bytes, e, g, -ivol, acc);
+          for (int j = 0; j < 4; ++j)
+            z[mt][v][j] = Mt[k] * T(acc[0][mt][v][j]) + Mt[3 + k] * T(acc[1][mt][v][j]) + Mt[6 + k] * T(acc[2][mt][v][j]);
+      finish_tail<Pr, MT, kTail4>(g, z);
+      if (e < mv.n_elem) store_tile<Pr, NP, MT>(zout + (size_t)(5 * k) * var_bytes, var_bytes, quad_bytes, e, g, -ivol, z);
     }
   }
 }
@@ -361,6 +380,7 @@ __global__ __launch_bounds__(256, (visc_min_blocks<P, Pr>())) void visc_kernel(V
   TDG_VISC_PROLOGUE
   const char* __restrict__ zbase = reinterpret_cast<const char*>(a.z);
   char* __restrict__ obase = reinterpret_cast<char*>(a.out);
+  S* __restrict__ hb = reinterpret_cast<S*>(a.hbuf);
   const T mu = T(a.mu), kappa = T(a.mu * a.gamma / ((a.gamma - 1.0) * a.prandtl));
   for (int64_t grp = g_begin + wave_x; grp < g_end; grp += waves_x) {
     const int e = (int)(grp * 16 + col);
@@ -441,7 +461,7 @@ __global__ __launch_bounds__(256, (visc_min_blocks<P, Pr>())) void visc_kernel(V
       }
     }
 
-    // ---------------- faces: Sv = sum_f int (F_v- + F_v+)/2 . N phi, lifted as two halves
+    // ---------------- faces: Sv = sum_f int (F_v- + F_v+)/2 . N phi, the own half here
 #pragma unroll 1
     for (int f = 0; f < 4; ++f) {
       T N[3];
@@ -473,50 +493,11 @@ __global__ __launch_bounds__(256, (visc_min_blocks<P, Pr>())) void visc_kernel(V
 #pragma unroll
             for (int v = 0; v < 5; ++v) h[v] = q < NF ? T(0.5) * h[v] : T(0);
             lift_point<Pr, MT, kTail4, L>(tab, f, ft, j, lane, g, h, acc);
-          }
-        }
-        // neighbour half: its traces through its own face table f+ (masked per column)
-        if (__any(nbf >= 0)) {
-          const uint32_t noff = (uint32_t)(nbf >= 0 ? nbf : e) * 4 * sizeof(S);
-          Acc vals[4][5];
-          zero(vals);
-          // each operand is read once and applied through every face table present in the
-          // tile, masked to the columns whose neighbour uses that table
-          bool mine[4], any[4];
+            // the own half of an interior face, for the neighbour's side of this face
+            if (nbf >= 0 && q < NF && e < mv.n_elem) {
 #pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            mine[c] = nbf >= 0 && fpl == c;
-            any[c] = __any(mine[c]);
-          }
-#pragma unroll
-          for (int w = 0; w < 4; ++w) {
-            const char* src = w == 0 ? ubase : zbase + (size_t)(5 * (w - 1)) * var_bytes;
-#pragma unroll
-            for (int v = 0; v < 5; ++v) {
-              Op b[1][KS];
-              load_operands<Pr, NP, KS, 1>(src + (size_t)v * var_bytes, var_bytes, noff, om, b);
-#pragma unroll
-              for (int c = 0; c < 4; ++c) {
-                if (any[c]) {
-#pragma unroll
-                  for (int s = 0; s < KS; ++s)
-                    vals[w][v] = Pr::mfma(tab[L::trace(c, ft, s) * 64 + lane], mine[c] ? b[0][s] : Op(0), vals[w][v]);
-                }
-              }
+              for (int v = 0; v < 5; ++v) hb[(((size_t)e * 4 + f) * 5 + v) * NF + q] = S(h[v]);
             }
-          }
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int q = 16 * ft + drow(Pr::f64, g, j);
-            T h[5] = {0, 0, 0, 0, 0};
-            if (nbf >= 0 && q < NF) {
-              T U[5], Z[3][5], Fv[3][5];
-              point(vals, j, U, Z);
-              visc_flux<T>(U, Z, gm1, mu, kappa, Fv);
-#pragma unroll
-              for (int v = 0; v < 5; ++v) h[v] = T(0.5) * (Fv[0][v] * N[0] + Fv[1][v] * N[1] + Fv[2][v] * N[2]);
-            }
-            lift_point<Pr, MT, kTail4, L>(tab, f, ft, j, lane, g, h, acc);
           }
         }
       }
@@ -524,6 +505,90 @@ __global__ __launch_bounds__(256, (visc_min_blocks<P, Pr>())) void visc_kernel(V
     finish_tail<Pr, MT, kTail4>(g, acc);
     // acc = Vv - Sv (the lift tables carry the face integral's minus sign): Rv = -acc / |K|
     if (e < mv.n_elem) store_tile<Pr, NP, MT>(obase, var_bytes, quad_bytes, e, g, -mv.inv_vol[e], acc);
+  }
+}
+
+// Neighbour halves of the viscous face term: Rv += -(sum_f int_f (F_v+ . N / 2) phi) / |K|
+// (with the lift tables' sign), where F_v+ . N / 2 at our face point q is minus the
+// neighbour's stored own half at point q of its face f+.
+// Light kernel: the lift tables are read through the caches (no LDS staging), so several
+// workgroups share a CU.
+template <int P, class Pr>
+__global__ __launch_bounds__(256) void visc_nbr_kernel(ViscArgs a) {
+  using O = Ord<P>;
+  using L = Layout<P, 1>;
+  using S = typename Pr::S;
+  using T = typename Pr::T;
+  using Op = typename Pr::Op;
+  using Acc = typename Pr::Acc;
+  constexpr int NP = O::NP, NF = O::NF, MT = O::MT, FT = O::FT;
+  constexpr int NPQ = npq_of(NP);
+  constexpr bool kTail4 = NP - 16 * (MT - 1) <= 4;
+  const Op* __restrict__ tab = reinterpret_cast<const Op*>(a.tab);
+  const int lane = threadIdx.x & 63, g = lane >> 4, col = lane & 15;
+  const MeshView& mv = a.mesh;
+  const int64_t epad = mv.epad;
+  const uint32_t quad_bytes = (uint32_t)(epad * 4 * sizeof(S));
+  const uint32_t var_bytes = quad_bytes * NPQ;
+  const int nblk = gridDim.x;
+  const int nwb = blockDim.x >> 6;
+  const int nx = (nblk % 8 == 0) ? 8 : 1;
+  const int xcd = blockIdx.x % nx;
+  const int64_t waves_x = (int64_t)(nblk / nx) * nwb;
+  const int64_t wave_x = (int64_t)(blockIdx.x / nx) * nwb + (threadIdx.x >> 6);
+  const int64_t ngroups = epad / 16;
+  const int64_t chunk = (ngroups + nx - 1) / nx;
+  const int64_t g_begin = xcd * chunk;
+  const int64_t g_end = g_begin + chunk < ngroups ? g_begin + chunk : ngroups;
+  const S* __restrict__ hb = reinterpret_cast<const S*>(a.hbuf);
+  char* __restrict__ obase = reinterpret_cast<char*>(a.out);
+  for (int64_t grp = g_begin + wave_x; grp < g_end; grp += waves_x) {
+    const int e = (int)(grp * 16 + col);
+    const int fcode = mv.fcode[e];
+    int nbr[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) nbr[f] = mv.nbr[f * epad + e];
+    Acc acc[MT][5];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int v = 0; v < 5; ++v) acc[mt][v] = Acc{0, 0, 0, 0};
+#pragma unroll 1
+    for (int f = 0; f < 4; ++f) {
+      const int nbf = f == 0 ? nbr[0] : f == 1 ? nbr[1] : f == 2 ? nbr[2] : nbr[3];
+      if (!__any(nbf >= 0)) continue;
+      const int fpl = (fcode >> (2 * f)) & 3;
+      const size_t rec = nbf >= 0 ? ((size_t)nbf * 4 + fpl) * 5 * NF : 0;
+#pragma unroll 1
+      for (int ft = 0; ft < FT; ++ft) {
+        T h[4][5];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int q = 16 * ft + drow(Pr::f64, g, j);
+#pragma unroll
+          for (int v = 0; v < 5; ++v) h[j][v] = (nbf >= 0 && q < NF) ? -T(hb[rec + (size_t)v * NF + q]) : T(0);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) lift_point<Pr, MT, kTail4, L>(tab, f, ft, j, lane, g, h[j], acc);
+      }
+    }
+    finish_tail<Pr, MT, kTail4>(g, acc);
+    if (e < mv.n_elem) {
+      const double scale = -mv.inv_vol[e];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int v = 0; v < 5; ++v)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int mode = 16 * mt + drow(Pr::f64, g, j);
+            if (mode < NP) {
+              S* o = reinterpret_cast<S*>(obase + (size_t)v * var_bytes + (uint32_t)(mode >> 2) * quad_bytes +
+                                          ((size_t)e * 4 + (mode & 3)) * sizeof(S));
+              *o = S(double(*o) + scale * double(acc[mt][v][j]));
+            }
+          }
+    }
   }
 }
 
@@ -566,6 +631,16 @@ hipError_t launch_visc(int p, int prec, const ViscArgs& a, hipStream_t stream) {
   if (p == PP)                                                                                  \
     return prec == 1 ? launch_visc_grid(visc_kernel<PP, PrecF32>, a, stream)                   \
                      : launch_visc_grid(visc_kernel<PP, PrecF64>, a, stream);
+  TDG_CASE(1) TDG_CASE(2) TDG_CASE(3) TDG_CASE(4)
+#undef TDG_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_visc_nbr(int p, int prec, const ViscArgs& a, hipStream_t stream) {
+#define TDG_CASE(PP)                                                                            \
+  if (p == PP)                                                                                  \
+    return prec == 1 ? launch_visc_grid(visc_nbr_kernel<PP, PrecF32>, a, stream)               \
+                     : launch_visc_grid(visc_nbr_kernel<PP, PrecF64>, a, stream);
   TDG_CASE(1) TDG_CASE(2) TDG_CASE(3) TDG_CASE(4)
 #undef TDG_CASE
   return hipErrorInvalidValue;

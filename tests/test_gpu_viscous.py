@@ -1,4 +1,4 @@
-"""GPU parity of the viscous (BR1) terms against the oracle: residual for p = 1..3 in
+"""GPU parity of the viscous (BR1) terms against the oracle: residual for p = 1..4 in
 FP64 and FP32 on a ragged periodic jittered mesh and with farfield / slip-wall faces,
 SSP-RK3 steps, and a uniform state (zero viscous residual)."""
 import math
@@ -16,7 +16,7 @@ TOL = {"fp64": 1e-12, "fp32": 1e-5}
 MU = 0.02
 
 
-@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_ns_residual(p, prec):
     mesh = make_mesh("ragged")
