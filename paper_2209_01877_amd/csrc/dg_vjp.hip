@@ -279,9 +279,10 @@ __device__ __forceinline__ void load_ops(const char* __restrict__ base, uint32_t
     }
 }
 
-// kRoe selects the face flux at compile time (Roe's adjoint needs more registers).
+// kRoe selects the face flux at compile time (Roe's adjoint needs more registers).  FP32 up
+// to P2 fits two waves per SIMD; FP64 and higher orders take one.
 template <int P, class Pr, bool kRoe>
-__global__ __launch_bounds__(256) void vjp_kernel(VjpArgs a) {
+__global__ __launch_bounds__(256, ((!Pr::f64 && P <= 2) ? 2 : 1)) void vjp_kernel(VjpArgs a) {
   using O = Ord<P>;
   using V = VjpLayout<P>;
   using S = typename Pr::S;
