@@ -146,8 +146,20 @@ class DG:
         vol = self.volume if elems is None else self.volume[elems]
         R = self.volume_term(U, elems) - self.face_term(U, elems)
         if self.mu > 0.0:
-            R = R - self.viscous_term(U, self.gradient(U), elems)
+            # the viscous face terms of `elems` read Z of the elements and of their neighbours
+            R = R - self.viscous_term(U, self.gradient(U, None if elems is None else self.with_neighbours(elems)), elems)
         return R / vol[:, None, None]
+
+    def with_neighbours(self, elems: torch.Tensor) -> torch.Tensor:
+        """The elements `elems` and every element sharing a face with one of them (sorted)."""
+        inside = torch.zeros(self.n_elem, dtype=torch.bool)
+        inside[elems] = True
+        interior = self.f_ep >= 0
+        ep = self.f_ep.clamp(min=0)
+        touch = inside.clone()
+        touch[self.f_em[interior & inside[ep]]] = True
+        touch[ep[interior & inside[self.f_em]]] = True
+        return torch.nonzero(touch).flatten()
 
     # --------------------------------------------------- viscous terms (BR1)
     def _face_traces(self, U: torch.Tensor, fi: torch.Tensor):
@@ -165,19 +177,28 @@ class DG:
             Up = torch.where(interior[:, None, None], Up, ghost)
         return em, ep, Bm, Bp, Um, Up, interior
 
-    def gradient(self, U: torch.Tensor) -> torch.Tensor:
+    def gradient(self, U: torch.Tensor, elems: torch.Tensor | None = None) -> torch.Tensor:
         """BR1 auxiliary variable Z = grad U, modal, (E, 3, 5, Np):
         |K| Z_i = -integral_K U grad phi_i + sum_f integral_f (U- + U+)/2 n phi_i
-        (the first equation of eq. 11 with the central interface value of Bassi and Rebay)."""
+        (the first equation of eq. 11 with the central interface value of Bassi and Rebay).
+        With `elems`, only those rows are complete (the volume terms of `elems` and the
+        faces touching them are evaluated; other rows are partial or zero)."""
         Z = torch.zeros((self.n_elem, 3) + tuple(U.shape[1:]), dtype=U.dtype)
-        for s in range(0, self.n_elem, self.chunk):
-            ks = torch.arange(s, min(s + self.chunk, self.n_elem))
+        idx = torch.arange(self.n_elem) if elems is None else elems
+        for s in range(0, idx.shape[0], self.chunk):
+            ks = idx[s:s + self.chunk]
             Uq = torch.einsum("qi,evi->eqv", self.B, U[ks])
             # d phi_i / d x_e = sum_d D_d jinv[d][e]
             Z[ks] -= self.absdet[ks, None, None, None] * torch.einsum(
                 "q,dqi,kde,kqv->kevi", self.w, self.D, self.jinv[ks], Uq)
-        for s in range(0, self.f_em.shape[0], self.chunk):
-            fi = torch.arange(s, min(s + self.chunk, self.f_em.shape[0]))
+        if elems is None:
+            faces = torch.arange(self.f_em.shape[0])
+        else:
+            inside = torch.zeros(self.n_elem, dtype=torch.bool)
+            inside[elems] = True
+            faces = torch.nonzero(inside[self.f_em] | ((self.f_ep >= 0) & inside[self.f_ep.clamp(min=0)])).flatten()
+        for s in range(0, faces.shape[0], self.chunk):
+            fi = faces[s:s + self.chunk]
             em, ep, Bm, Bp, Um, Up, interior = self._face_traces(U, fi)
             Uh = 0.5 * (Um + Up)
             scale = 2.0 * self.f_area[fi][:, None]

@@ -80,3 +80,29 @@ def test_c3_sampled_residual_vortex(c3, prec, tol):
     err = (R - R_ref).norm() / R_ref.norm()
     print(f"C3 vortex {prec}: sampled residual rel error {err:.3e}")
     assert err < tol
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_c2_sampled_navier_stokes_residual(prec, tol):
+    """Viscous (BR1) residual on the Navier-Stokes benchmark mesh (48^3 x 6, shuffled, Hilbert
+    order, the launch configuration the benchmark times) on sampled elements: the gradient,
+    viscous and neighbour-half kernels at full size against the oracle's sampled residual.
+    mu = 0.02 so that the viscous part is a visible share of R."""
+    mu = 0.02
+    mesh = kuhn_cube(48, length=10.0, shuffle_seed=2209, vid_seed=2210)
+    dg = oracle(3, mesh, mu=mu)
+    U = torch.from_numpy(fields.random_coefficients(mesh.n_elem, dg.Np, seed=23, scale=0.01))
+    s = solver(3, prec, mesh, renumber="hilbert", mu=mu)
+    R = s.get_state(s.residual(s.set_state(U.cuda())))
+    s.sync()
+    rng = np.random.default_rng(2)
+    sample = torch.from_numpy(np.sort(rng.choice(mesh.n_elem, 64, replace=False)))
+    R_ref = dg.residual(U, sample)
+    Rs = R[sample.cuda()].cpu()
+    err = (Rs - R_ref).norm() / R_ref.norm()
+    R_inv = oracle(3, mesh).residual(U, sample)
+    share = (R_ref - R_inv).norm() / R_ref.norm()
+    print(f"C2 Navier-Stokes {prec}: sampled residual rel error {err:.3e} (viscous share {share:.2e})")
+    assert share > 1e-3
+    assert err < tol
+    assert torch.isfinite(R).all()

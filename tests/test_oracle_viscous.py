@@ -118,3 +118,21 @@ def test_shear_wave_decay_rate():
         wq = dg.absdet[:, None] * dg.w[None, :]
         errs.append(float(((Rq - exact) ** 2 * wq).sum().sqrt() / ((exact ** 2) * wq).sum().sqrt()))
     assert errs[1] < 0.03 and errs[0] / errs[1] > 4.0, errs
+
+
+def test_sampled_residual_rows_match_the_full_residual():
+    """The sampled viscous residual (Z evaluated only on the sample and its face neighbours)
+    reproduces the rows of the full evaluation, on a jittered mesh with boundary faces."""
+    far = (1.0, 0.5, 0.1, 0.0, 1.0)
+    m = kuhn_cube(3, jitter=0.2, periodic=(False, True, True))
+    dg = DG(2, m.elem_vid, m.elem_xyz, m.bface_vid, m.bface_tag, farfield_prim=far, mu=0.03)
+    U = dg.project(fields.RandomSmooth(9))
+    full = dg.residual(U)
+    sample = torch.tensor([0, 5, 17, 40, 77, m.n_elem - 1])
+    part = dg.residual(U, sample)
+    assert (part - full[sample]).abs().max() <= 1e-13 * full.abs().max()
+    Z = dg.gradient(U)
+    Zs = dg.gradient(U, sample)
+    assert (Zs[sample] - Z[sample]).abs().max() <= 1e-13 * Z.abs().max()
+    nb = dg.with_neighbours(sample)
+    assert set(sample.tolist()) <= set(nb.tolist()) and nb.shape[0] > sample.shape[0]
