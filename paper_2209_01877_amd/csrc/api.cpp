@@ -466,8 +466,10 @@ int tdg_mesh_upload(tdg_ctx* c, int64_t n_elem, const int64_t* elem_vid, const d
       const size_t sb = (size_t)5 * ((c->ref.np + 3) / 4) * epad * 4 * (c->prec == TDG_FP32 ? 4 : 8);
       c->off_z = take(c->mu > 0.0 ? 3 * sb : 0);
       c->off_rv = take(c->mu > 0.0 ? sb : 0);
-      // own-half viscous face fluxes at the face points, 4 faces x 5 variables per element
-      const size_t hb = (size_t)epad * 4 * 5 * c->ref.fw.size() * (c->prec == TDG_FP32 ? 4 : 8);
+      // own-half viscous face fluxes at the face points (padded to whole 16-point tiles),
+      // 4 faces x 5 variables per element
+      const size_t nfp = (c->ref.fw.size() + 15) / 16 * 16;
+      const size_t hb = (size_t)epad * 4 * 5 * nfp * (c->prec == TDG_FP32 ? 4 : 8);
       c->off_hb = take(c->mu > 0.0 ? hb : 0);
     }
     c->total = off;

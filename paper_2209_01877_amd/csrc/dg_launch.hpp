@@ -59,7 +59,7 @@ struct ViscArgs {
   const void* tab;    // the stage kernel's operand tables (16x16x4 layout)
   double gamma, mu, prandtl;
   double far[5];      // farfield conserved state
-  void* hbuf;         // own-half viscous face fluxes, [E_pad][4 faces][5][N_f] (state precision)
+  void* hbuf;         // own-half viscous face fluxes, [E_pad][4 faces][5][16 FT] (state precision)
 };
 
 struct RefView {

@@ -493,10 +493,12 @@ __global__ __launch_bounds__(256, (visc_min_blocks<P, Pr>())) void visc_kernel(V
 #pragma unroll
             for (int v = 0; v < 5; ++v) h[v] = q < NF ? T(0.5) * h[v] : T(0);
             lift_point<Pr, MT, kTail4, L>(tab, f, ft, j, lane, g, h, acc);
-            // the own half of an interior face, for the neighbour's side of this face
-            if (nbf >= 0 && q < NF && e < mv.n_elem) {
+            // the own half of an interior face, for the neighbour's side of this face: per
+            // (element, face, variable) 16 FT values, the point held in register j of lane
+            // group g at 16 ft + 4 g + j, so that a reader's lane gets its four points at once
+            if (nbf >= 0 && e < mv.n_elem) {
 #pragma unroll
-              for (int v = 0; v < 5; ++v) hb[(((size_t)e * 4 + f) * 5 + v) * NF + q] = S(h[v]);
+              for (int v = 0; v < 5; ++v) hb[((((size_t)e * 4 + f) * 5 + v) * FT + ft) * 16 + 4 * g + j] = S(h[v]);
             }
           }
         }
@@ -558,15 +560,17 @@ __global__ __launch_bounds__(256) void visc_nbr_kernel(ViscArgs a) {
       const int nbf = f == 0 ? nbr[0] : f == 1 ? nbr[1] : f == 2 ? nbr[2] : nbr[3];
       if (!__any(nbf >= 0)) continue;
       const int fpl = (fcode >> (2 * f)) & 3;
-      const size_t rec = nbf >= 0 ? ((size_t)nbf * 4 + fpl) * 5 * NF : 0;
+      const size_t rec = nbf >= 0 ? ((size_t)nbf * 4 + fpl) * 5 * FT * 16 : 0;
+      typedef S s4_t __attribute__((ext_vector_type(4)));
 #pragma unroll 1
       for (int ft = 0; ft < FT; ++ft) {
         T h[4][5];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int q = 16 * ft + drow(Pr::f64, g, j);
+        for (int v = 0; v < 5; ++v) {
+          // the neighbour's values at points 16 ft + drow(g, j), j = 0..3 (zero past N_f)
+          const s4_t x = *reinterpret_cast<const s4_t*>(hb + rec + ((size_t)v * FT + ft) * 16 + 4 * g);
 #pragma unroll
-          for (int v = 0; v < 5; ++v) h[j][v] = (nbf >= 0 && q < NF) ? -T(hb[rec + (size_t)v * NF + q]) : T(0);
+          for (int j = 0; j < 4; ++j) h[j][v] = nbf >= 0 ? -T(x[j]) : T(0);
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) lift_point<Pr, MT, kTail4, L>(tab, f, ft, j, lane, g, h[j], acc);
