@@ -135,9 +135,11 @@ int tdg_set_flux(tdg_ctx* ctx, int flux);
  * flux is the average of both sides' viscous fluxes; boundary faces use the inviscid
  * ghost state with Z+ = Z-.  Stress by Stokes' hypothesis, heat flux -kappa grad T with
  * kappa = mu gamma / ((gamma - 1) Pr) and T = p / rho.  Every residual and RK entry point
- * then includes them (two more launches per stage: the lifting and the viscous residual
- * part, which the stage kernel adds).  Must be called before tdg_mesh_upload (the device
- * buffer then holds their scratch: four more states).  FP64 and FP32 modes; the mixed
+ * then includes them (three more launches per stage: the lifting, the volume and own-side
+ * face part of the viscous residual, and the neighbours' face halves; the stage kernel adds
+ * the result).  Must be called before tdg_mesh_upload (the device buffer then holds their
+ * scratch: four more states and each element's own-side viscous face fluxes at its face
+ * points, 4 x 5 x 16 ceil(N_f / 16) values).  FP64 and FP32 modes; the mixed
  * modes return TDG_ERR_UNSUPPORTED, and so do the adjoint entry points while mu > 0.
  * tdg_stable_dt stays the inviscid rule (the caller bounds dt by the viscous limit).
  * Errors: TDG_ERR_INVALID_ARG (mu < 0, Pr <= 0), TDG_ERR_STATE (mesh already uploaded). */
