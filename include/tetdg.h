@@ -31,9 +31,10 @@
  *   - Compute calls are asynchronous on the given hipStream_t (passed as void*,
  *     NULL = the null stream).  Kernel-side faults surface on the next
  *     synchronisation; tdg_sync_check() synchronises and reports them.
- *   - The library allocates no device memory after tdg_mesh_bind().  The mixed modes keep a
- *     scratch operand companion inside the bound mesh buffer, so calls on one context must
- *     not overlap in time (on different streams).
+ *   - The library allocates no device memory after tdg_mesh_bind().  The mixed modes (an
+ *     operand companion) and the viscous terms (Z, the viscous residual part, face fluxes)
+ *     keep scratch inside the bound mesh buffer, so calls on one context must not overlap
+ *     in time (on different streams).
  *   - A context is not thread-safe; distinct contexts are independent.
  *   - U, R, W and Ubar must not alias, except U in tdg_rk_step (updated in place).
  */
