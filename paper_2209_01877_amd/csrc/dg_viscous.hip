@@ -401,10 +401,9 @@ __global__ __launch_bounds__(256, (visc_min_blocks<P, Pr>())) void visc_kernel(V
 #pragma unroll
       for (int v = 0; v < 5; ++v) acc[mt][v] = Acc{0, 0, 0, 0};
 
-    // values of U (w = 0) and Z_k (w = 1 + k) of element el at the points of a tile, by
-    // table t(s), accumulated into out[w][v] (interpolation / trace contractions; with a
-    // mask, only the columns where it holds contribute)
-    auto gather = [&](uint32_t el_off, auto&& table, bool use, Acc (&out)[4][5]) {
+    // values of U (w = 0) and Z_k (w = 1 + k) of the element at the points of a tile, by
+    // table t(s), accumulated into out[w][v] (interpolation / trace contractions)
+    auto gather = [&](uint32_t el_off, auto&& table, Acc (&out)[4][5]) {
       // the element's own operands are the same in every tile: an opaque offset keeps their
       // loads inside the loop (hoisted out, 20 variables x KS operands stay live and spill)
       asm volatile("" : "+v"(el_off));
@@ -418,7 +417,7 @@ __global__ __launch_bounds__(256, (visc_min_blocks<P, Pr>())) void visc_kernel(V
 #pragma unroll
           for (int s = 0; s < KS; ++s) {
             const Op av = tab[table(s) * 64 + lane];
-            out[w][v] = Pr::mfma(av, use ? b[0][s] : Op(0), out[w][v]);
+            out[w][v] = Pr::mfma(av, b[0][s], out[w][v]);
           }
         }
       }
@@ -443,7 +442,7 @@ __global__ __launch_bounds__(256, (visc_min_blocks<P, Pr>())) void visc_kernel(V
     for (int qt = 0; qt < QT; ++qt) {
       Acc vals[4][5];
       zero(vals);
-      gather(eoff, [&](int s) { return L::interp(qt, s); }, true, vals);
+      gather(eoff, [&](int s) { return L::interp(qt, s); }, vals);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int q = 16 * qt + drow(Pr::f64, g, j);
@@ -474,7 +473,7 @@ __global__ __launch_bounds__(256, (visc_min_blocks<P, Pr>())) void visc_kernel(V
         {
           Acc vals[4][5];
           zero(vals);
-          gather(eoff, [&](int s) { return L::trace(f, ft, s); }, true, vals);
+          gather(eoff, [&](int s) { return L::trace(f, ft, s); }, vals);
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             const int q = 16 * ft + drow(Pr::f64, g, j);
