@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 from synthetic import fields, kuhn_cube  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+ALU_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}  # MI355X vector (fp64 = its MFMA rate)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_kernel_p3_64cube_traffic.json")
 KERNEL_SOURCES = ["dg_stage.hip", "dg_kernels.hpp", "dg_common.hpp", "dg_launch.hpp", "dg_tile.hpp"]
 
@@ -55,6 +56,15 @@ def measured_traffic(precision: str):
         return None
     r = d["per_precision"][precision]
     return (r["fetch_kib_per_dispatch"] * d["copy_fetch_factor"] + r["write_kib_per_dispatch"] * d["copy_write_factor"]) * 1024.0
+
+
+def stage_flops(p: int) -> float:
+    """Flops per element and stage of the element-centric path: contractions
+    2 * 5 * N_p * (4 N_q + 12 N_f) (volume interpolation, 3-direction projection, own and
+    neighbour traces, lift) and pointwise work 60 N_q + 100 * 4 N_f."""
+    np_ = (p + 1) * (p + 2) * (p + 3) // 6
+    nq, nf = (p + 1) ** 3, (p + 1) ** 2
+    return 2.0 * 5 * np_ * (4 * nq + 12 * nf) + 60.0 * nq + 400.0 * nf
 
 
 def stage_bytes(n_elem: int, n_modes: int, state_bytes: int) -> float:
@@ -132,6 +142,10 @@ def run_gpu(args):
             "stage_hbm_gb_per_s": stage_bytes(mesh.n_elem, s.n_modes, sb) * args.steps / t / 1e9,
             "upload_s": upload_s,
         }
+        if prec in ALU_PEAK_TFLOPS:  # the FP64 and FP32 paths against their ALU roof
+            tf = stage_flops(p) * mesh.n_elem * stages / t / 1e12
+            results[prec]["alu_tflops"] = tf
+            results[prec]["alu_frac"] = tf / ALU_PEAK_TFLOPS[prec]
         del s, U, U0, work, R
         torch.cuda.empty_cache()
     if "fp64" in states:
@@ -252,13 +266,35 @@ def cpu_baseline(p: int, n_cpu: int, steps: int):
         U = dg.rk3_step(U, dt)
     t = time.time() - t0
     dof = mesh.n_elem * dg.Np * 5
+    cores = torch.get_num_threads()
+    # the same oracle on one thread (the paper's serial baseline), on a smaller sample
+    n1 = 14
+    torch.set_num_threads(1)
+    mesh1 = kuhn_cube(n1, length=10.0, shuffle_seed=2209, vid_seed=2210)
+    dg1 = DG(p, mesh1.elem_vid, mesh1.elem_xyz)
+    U1 = dg1.project(lambda x: fields.isentropic_vortex(x, length=10.0))
+    dt1 = 0.2 * 0.41 * (10.0 / n1) / ((2 * p + 1) * 3.1)
+    U1 = dg1.rk3_step(U1, dt1)
+    t1 = time.time()
+    U1 = dg1.rk3_step(U1, dt1)
+    t1 = time.time() - t1
+    torch.set_num_threads(cores)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {
         "value": dof * 3 * steps / t / 1e9,
         "unit": "GDOF/s per RK stage",
-        "cores": torch.get_num_threads(),
+        "cores": cores,
         "kind": "oracle",
         "sample": f"P3 vortex on {n_cpu}^3 x 6 = {mesh.n_elem} tets, {steps} SSP-RK3 steps, fp64 torch-CPU, "
                   f"face-centric, untuned ({t:.1f} s)",
+        "cpu_model": model,
+        "single_thread": {"value": mesh1.n_elem * dg1.Np * 5 * 3 / t1 / 1e9, "unit": "GDOF/s per RK stage",
+                          "sample": f"P3 vortex on {n1}^3 x 6 = {mesh1.n_elem} tets, 1 SSP-RK3 step ({t1:.1f} s)"},
     }
 
 
@@ -286,10 +322,27 @@ def stream_ceiling(nbytes: int = 1 << 30, reps: int = 5) -> dict:
             raise RuntimeError("stream probe: the copy differs from its source")
     if torch.count_nonzero(dst).item() != 0:  # the last pass was the zero fill
         raise RuntimeError("stream probe: the zero fill left non-zero data")
-    del src, dst
+    # last-level cache (256 MB MALL): cached reads of a 128 MiB buffer, larger than the 8 x 4 MB
+    # of L2, after one pass that brings it in; 10 back-to-back launches between the events,
+    # so the launch gaps count against it (a lower bound)
+    mall_bytes = 128 << 20
+    msrc = src[: mall_bytes // 4]
+    stream_probe("read_cached", msrc, dst)
+    best = math.inf
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            stream_probe("read_cached", msrc, dst)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    out["mall_read"] = 10 * mall_bytes / best / 1e9
+    del src, dst, msrc
     torch.cuda.empty_cache()
-    return {"copy": out["copy"], "read": out["read"], "write": out["write"], "unit": "GB/s",
-            "buffer_bytes": nbytes, "method": f"best of {reps}, 16-byte non-temporal accesses"}
+    return {"copy": out["copy"], "read": out["read"], "write": out["write"], "mall_read": out["mall_read"],
+            "unit": "GB/s", "buffer_bytes": nbytes, "mall_buffer_bytes": mall_bytes,
+            "method": f"best of {reps}, 16-byte accesses (non-temporal except mall_read)"}
 
 
 def main():

@@ -253,7 +253,9 @@ int tdg_sync_check(tdg_ctx* ctx, void* hip_stream);
 /* Streaming probe: the practical DRAM bandwidth that the roofline model of Sec. IV.A bounds
  * a memory-bound kernel by, measured with 16-byte non-temporal accesses over caller device
  * buffers (grid-strided, 512-thread workgroups).  kind 0 copies src to dst, kind 1 only reads
- * src (dst: at least 16 bytes, whose first 16 may be overwritten), kind 2 zero-fills dst.
+ * src (dst: at least 16 bytes, whose first 16 may be overwritten), kind 2 zero-fills dst,
+ * kind 3 reads like kind 1 with ordinary cache-allocating loads (over a buffer that fits the
+ * last-level cache, repeated calls measure that cache's bandwidth).
  * bytes: a positive multiple of 16; src and dst 16-byte aligned and not overlapping (src may
  * be NULL for kind 2).  Asynchronous on hip_stream; no context, no allocation.  Errors:
  * TDG_ERR_INVALID_ARG (checked before any device call), TDG_ERR_HIP (launch failure). */

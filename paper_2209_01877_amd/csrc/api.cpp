@@ -893,7 +893,7 @@ int tdg_sync_check(tdg_ctx* c, void* s) {
 }
 
 int tdg_stream_probe(int kind, const void* src, void* dst, size_t bytes, void* s) {
-  if (kind < 0 || kind > 2 || bytes == 0 || bytes % 16 != 0 || !dst || (kind != 2 && !src)) return TDG_ERR_INVALID_ARG;
+  if (kind < 0 || kind > 3 || bytes == 0 || bytes % 16 != 0 || !dst || (kind != 2 && !src)) return TDG_ERR_INVALID_ARG;
   if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16 != 0) return TDG_ERR_INVALID_ARG;
   return launch_stream_probe(kind, src, dst, bytes, (hipStream_t)s) == hipSuccess ? TDG_OK : TDG_ERR_HIP;
 }

@@ -160,9 +160,11 @@ inline int np_of(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 
-// Streaming probe: 16-byte non-temporal accesses over caller buffers, grid-strided.
-// kind 0 copies src to dst, kind 1 reads src (its XOR reduction reaches dst[0] only for one
-// bit pattern, so the loads stay live), kind 2 zero-fills dst.
+// Streaming probe: 16-byte accesses over caller buffers, grid-strided, non-temporal except
+// kind 3.  kind 0 copies src to dst, kind 1 reads src (its XOR reduction reaches dst[0] only
+// for one bit pattern, so the loads stay live), kind 2 zero-fills dst, kind 3 reads src with
+// ordinary (cache-allocating) loads: repeated over a buffer that fits the last-level cache,
+// it measures that cache's bandwidth.
 typedef unsigned stream_u4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(512) void stream_kernel(int kind, const stream_u4* __restrict__ src,
                                                      stream_u4* __restrict__ dst, int64_t n16) {
@@ -170,9 +172,12 @@ __global__ __launch_bounds__(512) void stream_kernel(int kind, const stream_u4* 
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (kind == 0) {
     for (; i < n16; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
-  } else if (kind == 1) {
+  } else if (kind == 1 || kind == 3) {
     stream_u4 x = {0u, 0u, 0u, 0u};
-    for (; i < n16; i += stride) x ^= __builtin_nontemporal_load(src + i);
+    if (kind == 1)
+      for (; i < n16; i += stride) x ^= __builtin_nontemporal_load(src + i);
+    else
+      for (; i < n16; i += stride) x ^= src[i];
     if (x[0] == 0x9e3779b9u && x[1] == 0x7f4a7c15u && x[2] == 0xf39cc060u && x[3] == 0x5ced1e02u) dst[0] = x;
   } else {
     const stream_u4 z = {0u, 0u, 0u, 0u};

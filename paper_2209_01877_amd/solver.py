@@ -259,20 +259,21 @@ def debug_tables(p: int, which: int) -> np.ndarray:
     return out
 
 
-STREAM_KINDS = {"copy": 0, "read": 1, "write": 2}
+STREAM_KINDS = {"copy": 0, "read": 1, "write": 2, "read_cached": 3}
 
 
 def stream_probe(kind: str, src: torch.Tensor | None, dst: torch.Tensor, stream=None) -> None:
-    """One streaming pass (see tdg_stream_probe): "copy" src into dst (dst's bytes), "read" all
-    of src (dst: at least 16 bytes, may be overwritten) or "write" zeros over dst.  Device
-    tensors; asynchronous on the stream."""
+    """One streaming pass (see tdg_stream_probe): "copy" src into dst (dst's bytes), "read" or
+    "read_cached" all of src (dst: at least 16 bytes, may be overwritten) or "write" zeros
+    over dst.  Device tensors; asynchronous on the stream."""
     def nbytes(t):
         return t.numel() * t.element_size()
     if kind == "copy" and (src is None or nbytes(src) < nbytes(dst)):
         raise ValueError("stream_probe: src must hold at least dst's bytes")
-    if kind == "read" and (src is None or nbytes(dst) < 16):
+    reads = kind in ("read", "read_cached")
+    if reads and (src is None or nbytes(dst) < 16):
         raise ValueError("stream_probe: read needs src and a 16-byte dst")
-    n = nbytes(src) if kind == "read" else nbytes(dst)
+    n = nbytes(src) if reads else nbytes(dst)
     code = lib.tdg_stream_probe(STREAM_KINDS[kind], None if src is None else _ptr(src), _ptr(dst), n,
                                 _stream(stream))
     check(code, None, f"tdg_stream_probe({kind})")

@@ -211,12 +211,13 @@ def test_stream_probe_argument_errors():
     f = _lib.lib.tdg_stream_probe
     buf = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation
     odd = ctypes.c_void_p(0x1008)
-    assert f(3, buf, buf, 1024, None) == -1  # unknown kind
+    assert f(4, buf, buf, 1024, None) == -1  # unknown kind
     assert f(-1, buf, buf, 1024, None) == -1
     assert f(0, buf, buf, 0, None) == -1  # empty
     assert f(0, buf, buf, 1000, None) == -1  # not a multiple of 16 bytes
     assert f(0, None, buf, 1024, None) == -1  # copy without a source
     assert f(1, None, buf, 1024, None) == -1  # read without a source
+    assert f(3, None, buf, 1024, None) == -1
     assert f(2, None, None, 1024, None) == -1  # write without a destination
     assert f(0, odd, buf, 1024, None) == -1  # misaligned
     assert f(2, None, odd, 1024, None) == -1

@@ -22,6 +22,7 @@ def test_stream_probe_copy_and_fill(n16):
     torch.cuda.synchronize()
     assert torch.count_nonzero(dst).item() == 0
     stream_probe("read", src, guard)  # reads only; the guard is at most overwritten in its first 16 bytes
+    stream_probe("read_cached", src, guard)
     torch.cuda.synchronize()
     assert torch.equal(guard[4:], torch.full((4,), 5, dtype=torch.int32, device="cuda"))
 
