@@ -195,6 +195,79 @@ def run_p4(args):
     return out
 
 
+def run_roe(args):
+    """The paper's own interface flux (Roe) on the main workload (P3 vortex, 64^3 x 6): GDOF/s
+    per stage in bf16, fp32 and fp64, and the bf16/fp32 states after the timed steps against
+    the fp64 Roe state."""
+    from paper_2209_01877_amd import Solver
+
+    mesh = kuhn_cube(args.n, length=10.0, shuffle_seed=2209, vid_seed=2210)
+    p = args.p
+    dt = 0.2 * 0.41 * (10.0 / args.n) / ((2 * p + 1) * 3.1)
+    vortex = lambda x: fields.isentropic_vortex(x, length=10.0, beta=5.0, mach=0.5)  # noqa: E731
+    out, states = {}, {}
+    for prec in ["bf16", "fp32", "fp64"]:
+        s = Solver(p, prec)
+        s.upload(mesh, renumber=args.renumber)
+        s.set_flux("roe")
+        U = s.project_fn(vortex)
+        work = s.new_work()
+        U0 = U.clone()
+        s.rk_step(U, dt, args.warmup, work)
+        t = timed(lambda: s.rk_step(U, dt, args.steps, work), 1, 0)
+        U.copy_(U0)
+        s.rk_step(U, dt, args.steps, work)
+        states[prec] = s.get_state(U)
+        s.sync()
+        out[prec] = {"gdof_per_s_per_stage": mesh.n_elem * s.n_modes * 5 * 3 * args.steps / t / 1e9}
+        del s, U, U0, work
+        torch.cuda.empty_cache()
+    for prec in out:
+        out[prec].update(l2_errors(states[prec], states["fp64"]))
+    out["workload"] = (f"isentropic vortex, P{p}, periodic {args.n}^3 x 6 ({mesh.n_elem} tets), Roe flux, "
+                       f"{args.steps} SSP-RK3 steps")
+    return out
+
+
+def run_temporal_mixed(args):
+    """The paper's temporal mixed precision (Sec. III.B, Table 2) on the main workload: of
+    `steps` SSP-RK3 steps the first N run in a low precision and the rest in FP64 (state
+    handed over through the caller layout).  Time per step and the final state's difference
+    from the all-FP64 run, for N = 0, steps/2 and steps with bf16 and fp32."""
+    from paper_2209_01877_amd.schedule import TemporalMixed
+
+    mesh = kuhn_cube(args.n, length=10.0, shuffle_seed=2209, vid_seed=2210)
+    p = args.p
+    n = args.steps
+    dt = 0.2 * 0.41 * (10.0 / args.n) / ((2 * p + 1) * 3.1)
+    vortex = lambda x: fields.isentropic_vortex(x, length=10.0, beta=5.0, mach=0.5)  # noqa: E731
+    out = {}
+    ref = None
+    for low in ["bf16", "fp32"]:
+        tm = TemporalMixed(p, mesh, low=low, renumber=args.renumber)
+        U0 = tm.high.get_state(tm.high.project_fn(vortex))
+        tm.run(U0, dt, 1, 2)  # warm-up of both contexts
+        for n_low in (0, n // 2, n):
+            if low == "fp32" and n_low == 0:
+                continue  # the all-FP64 run does not depend on the low precision
+            start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            start.record()
+            U = tm.run(U0, dt, n_low, n)
+            stop.record()
+            torch.cuda.synchronize()
+            t = start.elapsed_time(stop) / 1e3
+            if n_low == 0:
+                ref = U
+            key = "fp64" if n_low == 0 else f"{low}_first_{n_low}"
+            out[key] = {"ms_per_step": 1e3 * t / n, **l2_errors(U, ref)}
+        del tm, U0, U
+        torch.cuda.empty_cache()
+    out["workload"] = (f"isentropic vortex, P{p}, periodic {args.n}^3 x 6 ({mesh.n_elem} tets), {n} SSP-RK3 "
+                       "steps, the first N in a low precision (includes the hand-over)")
+    return out
+
+
 def run_navier_stokes(args):
     """Viscous (BR1) form: P3 vortex on 48^3 x 6 with mu = 1e-3, FP64 and FP32: GDOF/s per
     SSP-RK3 stage with the viscous terms, beside the same workload without them."""
@@ -357,8 +430,8 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=28)
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the P4, adjoint and Navier-Stokes workloads")
-    ap.add_argument("--extras", default="p4,adjoint,navier_stokes", help="which of those to run")
+    ap.add_argument("--no-extra", action="store_true", help="skip the extra workloads (--extras)")
+    ap.add_argument("--extras", default="p4,adjoint,navier_stokes,roe,temporal_mixed", help="which of those to run")
     ap.add_argument("--copy-calibration", action="store_true", help="run a 1 GiB device copy first")
     args = ap.parse_args()
     args.precisions = args.precisions.split(",")
@@ -433,6 +506,10 @@ def main():
         line["adjoint_over_forward_fp64"] = line["adjoint"]["fp64"]["adjoint_over_forward"]
     if "navier_stokes" in extras:
         line["navier_stokes"] = run_navier_stokes(args)
+    if "roe" in extras:
+        line["roe_flux"] = run_roe(args)
+    if "temporal_mixed" in extras:
+        line["temporal_mixed_precision"] = run_temporal_mixed(args)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args.p, args.cpu_n, args.cpu_steps)
     print(json.dumps(line), flush=True)
