@@ -106,3 +106,27 @@ def test_c2_sampled_navier_stokes_residual(prec, tol):
     assert share > 1e-3
     assert err < tol
     assert torch.isfinite(R).all()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5), ("bf16", 5e-2), ("fp16", 1e-2)])
+def test_c3b_sampled_stage_p4(prec, tol):
+    """The P4 precision-form workload (40^3 x 6 = 384,000 tets, shuffled, Hilbert order, the
+    launch configuration the benchmark's P4 leg times): one SSP-RK3 stage on a random state,
+    sampled elements against the oracle (error relative to the stage's residual part)."""
+    mesh = kuhn_cube(40, length=10.0, shuffle_seed=2209, vid_seed=2210)
+    dg = oracle(4, mesh)
+    U = torch.from_numpy(fields.random_coefficients(mesh.n_elem, dg.Np, seed=31, scale=0.01))
+    U0 = torch.from_numpy(fields.random_coefficients(mesh.n_elem, dg.Np, seed=32, scale=0.01))
+    s = solver(4, prec, mesh, renumber="hilbert")
+    out = s.rk_stage(s.set_state(U.cuda()), s.set_state(U0.cuda()), s.new_state(), 0.75, 1.0)
+    rng = np.random.default_rng(4)
+    sample = torch.from_numpy(np.sort(rng.choice(mesh.n_elem, 64, replace=False)))
+    got = s.get_state(out)[sample.cuda()].cpu()
+    s.sync()
+    R_ref = dg.residual(U, sample)
+    if prec == "fp32":  # the stage inputs are stored in fp32
+        U, U0 = U.float().double(), U0.float().double()
+    ref = 0.75 * U0[sample] + 0.25 * (U[sample] + R_ref)
+    err = (got - ref).norm() / (0.25 * R_ref.norm())
+    print(f"C3b P4 {prec}: sampled stage rel error {err:.3e}")
+    assert err < tol

@@ -32,8 +32,8 @@ def test_residual_random_state(p, prec):
     assert err < TOL[prec]
 
 
-@pytest.mark.parametrize("p", [1, 2, 3])
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16", "fp16"])
 def test_residual_with_boundaries(p, prec):
     far = (1.0, 0.5 * math.sqrt(1.4), 0.0, 0.0, 1.0)
     mesh = make_mesh("bump")
