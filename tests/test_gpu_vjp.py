@@ -41,7 +41,7 @@ def test_vjp_vs_oracle(p, prec):
     assert err < TOL[prec]
 
 
-@pytest.mark.parametrize("p", [2, 3])
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
 def test_vjp_boundaries(p):
     far = (1.0, 0.5 * math.sqrt(1.4), 0.0, 0.0, 1.0)
     mesh = make_mesh("bump")
@@ -69,7 +69,7 @@ def sonic_state(n_elem, n_modes, seed):
     return torch.from_numpy(U)
 
 
-@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("state", ["subsonic", "sonic"])
 def test_roe_vjp_vs_oracle(p, prec, state):
