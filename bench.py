@@ -7,9 +7,11 @@ Hilbert curve.  One step = one SSP-RK3 step = three fused residual+update launch
 
 The headline value is the mixed bf16 path (bf16 MFMA contractions with fp32 accumulation,
 fp32 fluxes, fp64 state); the same workload is also timed in fp32, fp16-mixed and fp64, the
-residual-only kernel is timed, and the mixed result after the timed steps is compared with
-the fp64 GPU result (relative L2 per variable).  cpu_baseline is the FP64 CPU oracle on a
-16^3 x 6 sample of the same problem.
+residual entry point is timed, and each precision's state after the timed steps is compared
+with the fp64 GPU result (relative L2 per variable).  cpu_baseline is the FP64 CPU oracle on
+a 28^3 x 6 sample of the same problem (all host threads; one thread on a 14^3 x 6 sample).
+stream_ceiling is the practical bandwidth of the box; the extra workloads (--extras) are P4,
+the adjoint, the viscous terms, Roe's flux and temporal mixed precision.
 """
 from __future__ import annotations
 
@@ -76,6 +78,13 @@ def stage_bytes(n_elem: int, n_modes: int, state_bytes: int) -> float:
     return float(n_elem) * per_elem
 
 
+def residual_bytes(n_elem: int, n_modes: int, state_bytes: int) -> float:
+    """Algorithmic HBM bytes of one residual evaluation: the state read, R written, geometry
+    and topology per element (1,700 B at P3 with an fp64 state)."""
+    st = 5 * n_modes * state_bytes
+    return float(n_elem) * (2 * st + 80 + 20)
+
+
 def timed(fn, steps: int, warmup: int) -> float:
     for _ in range(warmup):
         fn()
@@ -139,6 +148,10 @@ def run_gpu(args):
             "dual_phase_gdof_per_s_per_stage": dof * stages / (t_long - t_short) / 1e9,
             "residual_gdof_per_s": dof * args.steps / tr / 1e9,
             "residual_ms": 1e3 * tr / args.steps,
+            # the residual entry point (in the mixed modes: companion pack + residual kernel)
+            # against the HBM roof on its algorithmic bytes
+            "residual_hbm_gb_per_s": residual_bytes(mesh.n_elem, s.n_modes, sb) * args.steps / tr / 1e9,
+            "residual_hbm_frac": residual_bytes(mesh.n_elem, s.n_modes, sb) * args.steps / tr / 1e9 / HBM_PEAK_GBS,
             "stage_hbm_gb_per_s": stage_bytes(mesh.n_elem, s.n_modes, sb) * args.steps / t / 1e9,
             "upload_s": upload_s,
         }
