@@ -11,10 +11,11 @@ pytestmark = pytest.mark.gpu
 from gpu_common import make_mesh, solver  # noqa: E402
 
 
-@pytest.mark.parametrize("prec", ["fp64", "bf16"])
-def test_rk_steps_in_a_graph(prec):
+@pytest.mark.parametrize("prec,mu", [("fp64", 0.0), ("bf16", 0.0), ("fp64", 0.02), ("fp32", 0.02)])
+def test_rk_steps_in_a_graph(prec, mu):
+    """mu > 0 adds the viscous launches (lifting, viscous part, neighbour halves) per stage."""
     mesh = make_mesh("jitter4")
-    s = solver(2, prec, mesh)
+    s = solver(2, prec, mesh, mu=mu)
     U0 = s.project_fn(lambda z: fields.RandomSmooth(11)(z))
     dt = 1e-3
     work = s.new_work()
