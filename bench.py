@@ -11,7 +11,8 @@ residual entry point is timed, and each precision's state after the timed steps 
 with the fp64 GPU result (relative L2 per variable).  cpu_baseline is the FP64 CPU oracle on
 a 28^3 x 6 sample of the same problem (all host threads; one thread on a 14^3 x 6 sample).
 stream_ceiling is the practical bandwidth of the box; the extra workloads (--extras) are P4,
-the adjoint, the viscous terms, Roe's flux and temporal mixed precision.
+the adjoint, the viscous terms, Roe's flux, temporal mixed precision and graph replay
+on the smallest mesh.
 """
 from __future__ import annotations
 
@@ -281,6 +282,43 @@ def run_temporal_mixed(args):
     return out
 
 
+def run_small_graph(args):
+    """Launch-bound case: P1 density wave on the 4^3 x 6 = 384-tet cube (the smallest
+    configuration), 100 SSP-RK3 steps per call, FP64 and bf16: eager launches against a
+    replay of the same 100 steps captured in a HIP graph (best of 5 each)."""
+    from paper_2209_01877_amd import Solver
+
+    mesh = kuhn_cube(4)
+    out = {}
+    n = 100
+    for prec in ["fp64", "bf16"]:
+        s = Solver(1, prec)
+        s.upload(mesh, renumber=args.renumber)
+        U0 = s.project_fn(lambda x: fields.sine_wave(x))
+        dt = 2.26e-3
+        work = s.new_work()
+        U = U0.clone()
+        s.rk_step(U, dt, n, work)
+        t_eager = min(timed(lambda: s.rk_step(U, dt, n, work), 1, 0) for _ in range(5))
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            s.rk_step(U, dt, n, work)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            s.rk_step(U, dt, n, work)
+        g.replay()
+        t_graph = min(timed(g.replay, 1, 0) for _ in range(5))
+        out[prec] = {"eager_us_per_step": 1e6 * t_eager / n, "graph_us_per_step": 1e6 * t_graph / n,
+                     "graph_speedup": t_eager / t_graph}
+        del g, s, U, U0, work
+        torch.cuda.empty_cache()
+    out["workload"] = f"density wave, P1, periodic 4^3 x 6 ({mesh.n_elem} tets), {n} SSP-RK3 steps per call"
+    return out
+
+
 def run_navier_stokes(args):
     """Viscous (BR1) form: P3 vortex on 48^3 x 6 with mu = 1e-3, FP64 and FP32: GDOF/s per
     SSP-RK3 stage with the viscous terms, beside the same workload without them."""
@@ -444,7 +482,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the extra workloads (--extras)")
-    ap.add_argument("--extras", default="p4,adjoint,navier_stokes,roe,temporal_mixed", help="which of those to run")
+    ap.add_argument("--extras", default="p4,adjoint,navier_stokes,roe,temporal_mixed,small_graph",
+                    help="which of those to run")
     ap.add_argument("--copy-calibration", action="store_true", help="run a 1 GiB device copy first")
     args = ap.parse_args()
     args.precisions = args.precisions.split(",")
@@ -523,6 +562,8 @@ def main():
         line["roe_flux"] = run_roe(args)
     if "temporal_mixed" in extras:
         line["temporal_mixed_precision"] = run_temporal_mixed(args)
+    if "small_graph" in extras:
+        line["small_mesh_graph"] = run_small_graph(args)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args.p, args.cpu_n, args.cpu_steps)
     print(json.dumps(line), flush=True)
