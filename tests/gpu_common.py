@@ -65,6 +65,53 @@ def rel_err(dg, a, b) -> float:
     return float((num / den).max())
 
 
+def elem_err(a: torch.Tensor, b: torch.Tensor, scale: torch.Tensor | None = None) -> torch.Tensor:
+    """Per variable: the largest element-wise difference max_{K,i} |a - b| divided by the
+    largest reference magnitude max_{K,i} |b| of that variable (or by `scale`, one value per
+    variable).  A variable whose reference is identically zero is measured in absolute terms.
+    Tensors are in the caller layout [elements][5][modes]."""
+    d = (a - b).abs().amax(dim=(0, 2))
+    s = b.abs().amax(dim=(0, 2)) if scale is None else scale.to(d)
+    s = torch.where(s > 0, s, torch.ones_like(s))
+    return d / s
+
+
+def weighted_l2_err(a: torch.Tensor, b: torch.Tensor, vol: torch.Tensor) -> torch.Tensor:
+    """Per variable normwise relative L2 error with element weights `vol` (the function-space
+    norm restricted to a sample of elements)."""
+    w = vol.to(a)[:, None, None]
+    num = torch.sqrt((w * (a - b) ** 2).sum((0, 2)))
+    den = torch.sqrt((w * b * b).sum((0, 2)))
+    den = torch.where(den > 0, den, torch.ones_like(den))
+    return num / den
+
+
+def assert_parity(dg, got: torch.Tensor, ref: torch.Tensor, tol: float, tol_elem: float | None = None,
+                  label: str = "", vol: torch.Tensor | None = None, l2_scale: torch.Tensor | None = None,
+                  elem_scale: torch.Tensor | None = None):
+    """Parity of a GPU result with the oracle's, per conserved variable, by two measures:
+    the normwise relative L2 error (function-space norm sum_K |K| sum_i c^2; `vol` restricts
+    it to sampled elements) below `tol`, and the element-wise error
+    max |got - ref| / max |ref| below `tol_elem` (default `tol`), so that an error confined
+    to a few elements cannot hide in the norm.  `l2_scale` / `elem_scale` replace the
+    per-variable reference sizes (e.g. by the whole state's) where a variable's own size is
+    noise.  Returns (largest L2 error, largest element-wise error)."""
+    if vol is None:
+        vol = dg.volume
+    if l2_scale is None:
+        l2 = weighted_l2_err(got, ref, vol)
+    else:
+        w = vol.to(got)[:, None, None]
+        l2 = torch.sqrt((w * (got - ref) ** 2).sum((0, 2))) / l2_scale
+    el = elem_err(got, ref, elem_scale)
+    te = tol if tol_elem is None else tol_elem
+    print(f"{label}: rel L2 {float(l2.max()):.3e} (per variable {' '.join(f'{x:.1e}' for x in l2.tolist())}), "
+          f"element-wise {float(el.max()):.3e}")
+    assert float(l2.max()) < tol, (label, l2.tolist())
+    assert float(el.max()) < te, (label, el.tolist())
+    return float(l2.max()), float(el.max())
+
+
 def zero_padding(s, X: torch.Tensor) -> torch.Tensor:
     """Zero the padding of an internal-layout state [5][ceil(Np/4)][E_pad][4] in place:
     elements past the mesh and the unused modes of the last mode quad."""

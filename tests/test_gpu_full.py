@@ -13,7 +13,7 @@ from synthetic import fields, kuhn_cube
 
 pytestmark = pytest.mark.gpu
 
-from gpu_common import make_mesh, oracle, random_state, rel_err, solver, zero_padding  # noqa: E402
+from gpu_common import assert_parity, make_mesh, oracle, random_state, solver, zero_padding  # noqa: E402
 
 FAR = (1.0, 0.5 * math.sqrt(1.4), 0.0, 0.0, 1.0)
 
@@ -32,7 +32,7 @@ def test_wall_pressure_and_gradient(p, prec):
     got = s.get_state(g).cpu()
     tol = 1e-13 if prec != "fp32" else 1e-6
     assert abs(J.item() - J_ref.item()) < tol * abs(J_ref.item())
-    assert rel_err(dg, got, g_ref) < (1e-12 if prec != "fp32" else 1e-6)
+    assert_parity(dg, got, g_ref, 1e-12 if prec != "fp32" else 1e-6, label=f"p={p} {prec} wall-pressure gradient")
 
 
 def test_objective_trajectory_adjoint_vs_oracle():
@@ -58,9 +58,7 @@ def test_objective_trajectory_adjoint_vs_oracle():
     _, gN = s.wall_pressure(UN.detach(), grad=True)
     (g0,) = torch.autograd.grad(UN, Ui, gN)
     got = s.get_state(g0.contiguous()).cpu()
-    err = rel_err(dg, got, ref)
-    print(f"objective trajectory adjoint rel L2 error {err:.3e}")
-    assert err < 1e-11
+    assert_parity(dg, got, ref, 1e-11, label="objective trajectory adjoint")
 
 
 def test_full_size_fifty_steps():

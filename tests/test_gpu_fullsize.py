@@ -9,7 +9,7 @@ from synthetic import fields, kuhn_cube
 
 pytestmark = pytest.mark.gpu
 
-from gpu_common import oracle, solver  # noqa: E402
+from gpu_common import assert_parity, oracle, solver  # noqa: E402
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
@@ -26,9 +26,7 @@ def test_c2_sampled_residual(prec, tol):
     sample = torch.from_numpy(np.sort(rng.choice(mesh.n_elem, 96, replace=False)))
     R_ref = dg.residual(U, sample)
     Rs = R[sample.cuda()].cpu()
-    err = (Rs - R_ref).norm() / R_ref.norm()
-    print(f"C2 {prec}: sampled residual rel error {err:.3e}")
-    assert err < tol
+    assert_parity(dg, Rs, R_ref, tol, vol=dg.volume[sample], label=f"C2 {prec} sampled residual")
     assert torch.isfinite(R).all()
 
 
@@ -61,9 +59,12 @@ def test_c3_sampled_stage(c3, prec, tol):
     if prec == "fp32":  # the stage inputs are stored in fp32
         U, U0 = U.float().double(), U0.float().double()
     ref = 0.75 * U0[sample] + 0.25 * (U[sample] + R_ref)
-    err = (got - ref).norm() / (0.25 * R_ref.norm())
-    print(f"C3 {prec}: sampled stage rel error {err:.3e}")
-    assert err < tol
+    # measured against the stage's residual part 0.25 R (dt = 1), per variable
+    vol = dg.volume[sample]
+    w = vol[:, None, None]
+    l2_scale = torch.sqrt((w * (0.25 * R_ref) ** 2).sum((0, 2)))
+    assert_parity(dg, got, ref, tol, vol=vol, l2_scale=l2_scale, elem_scale=(0.25 * R_ref).abs().amax((0, 2)),
+                  label=f"C3 {prec} sampled stage")
 
 
 @pytest.mark.parametrize("prec,tol", [("bf16", 0.1), ("fp16", 0.02)])
@@ -77,9 +78,12 @@ def test_c3_sampled_residual_vortex(c3, prec, tol):
     R = s.get_state(s.residual(s.set_state(U.cuda())))[sample.cuda()].cpu()
     s.sync()
     R_ref = dg.residual(U, sample)
-    err = (R - R_ref).norm() / R_ref.norm()
-    print(f"C3 vortex {prec}: sampled residual rel error {err:.3e}")
-    assert err < tol
+    # the vortex is uniform in z: the rho w residual is discretisation noise, so every variable
+    # is measured against the whole residual (pooled over the five variables)
+    vol = dg.volume[sample]
+    pooled = torch.sqrt((vol[:, None, None] * R_ref ** 2).sum())
+    assert_parity(dg, R, R_ref, tol, 3 * tol, vol=vol, l2_scale=pooled, elem_scale=R_ref.abs().max(),
+                  label=f"C3 vortex {prec} sampled residual")
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
@@ -99,12 +103,11 @@ def test_c2_sampled_navier_stokes_residual(prec, tol):
     sample = torch.from_numpy(np.sort(rng.choice(mesh.n_elem, 64, replace=False)))
     R_ref = dg.residual(U, sample)
     Rs = R[sample.cuda()].cpu()
-    err = (Rs - R_ref).norm() / R_ref.norm()
     R_inv = oracle(3, mesh).residual(U, sample)
     share = (R_ref - R_inv).norm() / R_ref.norm()
-    print(f"C2 Navier-Stokes {prec}: sampled residual rel error {err:.3e} (viscous share {share:.2e})")
+    print(f"C2 Navier-Stokes: viscous share {share:.2e}")
     assert share > 1e-3
-    assert err < tol
+    assert_parity(dg, Rs, R_ref, tol, vol=dg.volume[sample], label=f"C2 Navier-Stokes {prec} sampled residual")
     assert torch.isfinite(R).all()
 
 
@@ -127,6 +130,7 @@ def test_c3b_sampled_stage_p4(prec, tol):
     if prec == "fp32":  # the stage inputs are stored in fp32
         U, U0 = U.float().double(), U0.float().double()
     ref = 0.75 * U0[sample] + 0.25 * (U[sample] + R_ref)
-    err = (got - ref).norm() / (0.25 * R_ref.norm())
-    print(f"C3b P4 {prec}: sampled stage rel error {err:.3e}")
-    assert err < tol
+    vol = dg.volume[sample]
+    l2_scale = torch.sqrt((vol[:, None, None] * (0.25 * R_ref) ** 2).sum((0, 2)))
+    assert_parity(dg, got, ref, tol, vol=vol, l2_scale=l2_scale, elem_scale=(0.25 * R_ref).abs().amax((0, 2)),
+                  label=f"C3b P4 {prec} sampled stage")

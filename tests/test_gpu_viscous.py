@@ -10,7 +10,7 @@ from synthetic import fields
 
 pytestmark = pytest.mark.gpu
 
-from gpu_common import gpu_residual, make_mesh, oracle, random_state, rel_err, solver  # noqa: E402
+from gpu_common import assert_parity, gpu_residual, make_mesh, oracle, random_state, rel_err, solver  # noqa: E402
 
 TOL = {"fp64": 1e-12, "fp32": 1e-5}
 MU = 0.02
@@ -24,12 +24,11 @@ def test_ns_residual(p, prec):
     U = random_state(dg, seed=41)
     R_ref = dg.residual(U)
     s = solver(p, prec, mesh, mu=MU)
-    err = rel_err(dg, gpu_residual(s, U), R_ref)
+    got = gpu_residual(s, U)
     # the viscous part must matter at this scale for the test to mean anything
     dg0 = oracle(p, mesh)
     assert rel_err(dg, dg0.residual(U), R_ref) > 1e-3
-    print(f"NS p={p} {prec}: rel L2 error {err:.3e}")
-    assert err < TOL[prec]
+    assert_parity(dg, got, R_ref, TOL[prec], label=f"NS p={p} {prec}")
 
 
 @pytest.mark.parametrize("p", [2, 3])
@@ -40,9 +39,7 @@ def test_ns_residual_boundaries(p):
     U = random_state(dg, seed=42)
     R_ref = dg.residual(U)
     s = solver(p, "fp64", mesh, farfield=far, mu=MU)
-    err = rel_err(dg, gpu_residual(s, U), R_ref)
-    print(f"NS boundaries p={p}: rel L2 error {err:.3e}")
-    assert err < 1e-12
+    assert_parity(dg, gpu_residual(s, U), R_ref, 1e-12, label=f"NS boundaries p={p}")
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -59,9 +56,7 @@ def test_ns_rk_steps(prec):
     s.rk_step(Ui, dt, 3)
     got = s.get_state(Ui).cpu()
     s.sync()
-    err = rel_err(dg, got - U, ref - U)
-    print(f"NS rk {prec}: increment rel L2 error {err:.3e}")
-    assert err < TOL[prec]
+    assert_parity(dg, got - U, ref - U, TOL[prec], label=f"NS rk {prec}, increment")
 
 
 def test_ns_uniform_state():
@@ -85,9 +80,7 @@ def test_ns_residual_with_roe_flux(prec):
     R_ref = dg.residual(U)
     s = solver(2, prec, mesh, farfield=far, mu=MU)
     s.set_flux("roe")
-    err = rel_err(dg, gpu_residual(s, U), R_ref)
-    print(f"NS + Roe {prec}: rel L2 error {err:.3e}")
-    assert err < TOL[prec]
+    assert_parity(dg, gpu_residual(s, U), R_ref, TOL[prec], label=f"NS + Roe {prec}")
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -114,6 +107,4 @@ def test_ns_adaptive_steps(prec):
     got = s.get_state(Ui).cpu()
     s.sync()
     assert np.allclose(dts.cpu().numpy(), dts_ref, rtol={"fp64": 1e-13, "fp32": 1e-5}[prec], atol=0)
-    err = rel_err(dg, got - U, ref - U)
-    print(f"NS adaptive {prec}: increment rel L2 error {err:.3e}")
-    assert err < TOL[prec]
+    assert_parity(dg, got - U, ref - U, TOL[prec], label=f"NS adaptive {prec}, increment")
