@@ -165,9 +165,16 @@ int tdg_mesh_stats(const tdg_ctx* ctx, int64_t out[7]);
 int tdg_state_elems(const tdg_ctx* ctx, int64_t* n_elem_pad);
 int tdg_state_bytes(const tdg_ctx* ctx, size_t* bytes);
 
-/* User (device, double) -> internal (device).  Padding elements are set to a copy of element 0. */
+/* The state is the set of coefficients c_j of the modal expansion U_h = sum_j c_j phi_j of
+ * each conserved variable on each element (Sec. II.B, eq. 10); these two calls only move
+ * it between the caller's layout and the internal one, without arithmetic.
+ * User (device, double) -> internal (device): padding elements are set to a copy of
+ * element 0 (FP32 mode: each coefficient rounded to float).  U_user: device double
+ * [n_elem][5][N_p], caller-owned, read; U_int: device, tdg_state_bytes() bytes, written.
+ * Errors: TDG_ERR_STATE (no bound mesh), TDG_ERR_INVALID_ARG (NULL), TDG_ERR_HIP. */
 int tdg_set_state(tdg_ctx* ctx, const double* U_user, void* U_int, void* hip_stream);
-/* Internal (device) -> user (device, double). */
+/* Internal (device) -> user (device, double [n_elem][5][N_p], caller's element order,
+ * overwritten).  Errors as tdg_set_state. */
 int tdg_get_state(tdg_ctx* ctx, const void* U_int, double* U_user, void* hip_stream);
 
 /* Physical coordinates of the volume quadrature points, device double [n_elem][N_q][3],
@@ -187,11 +194,15 @@ int tdg_project(tdg_ctx* ctx, const double* prim_user, void* U_int, void* hip_st
  * the face integral reaches both neighbours without atomics.  R has U's layout. */
 int tdg_residual(tdg_ctx* ctx, const void* U, void* R, void* hip_stream);
 
-/* n_steps SSP-RK3 steps of size dt on U (internal, in place):
+/* The time loop of Sec. III (opening passage): the semi-discrete system dc/dt = R(c) of
+ * eq. 11 is advanced by an explicit Runge-Kutta scheme with one right-hand-side evaluation
+ * per stage (the paper uses second order; this library the three-stage SSP scheme).
+ * n_steps SSP-RK3 steps of size dt on U (internal, in place):
  *   U1 = U + dt R(U);  U2 = 3/4 U + 1/4 (U1 + dt R(U1));  U <- 1/3 U + 2/3 (U2 + dt R(U2)).
  * work: device buffer of tdg_work_bytes() bytes (two internal states, plus in the mixed
  * modes three low-precision operand companions).  One fused residual+update launch per
- * stage (mixed modes: plus one companion pass over U per call). */
+ * stage (mixed modes: plus one companion pass over U per call).
+ * Errors: TDG_ERR_INVALID_ARG (NULL U or work, n_steps < 0), TDG_ERR_STATE, TDG_ERR_HIP. */
 int tdg_rk_step(tdg_ctx* ctx, void* U, void* work, double dt, int n_steps, void* hip_stream);
 
 /* n_steps SSP-RK3 steps with the step size chosen on the device before every step
@@ -200,6 +211,9 @@ int tdg_rk_step(tdg_ctx* ctx, void* U, void* work, double dt, int n_steps, void*
  * with the cell means of the current U (as tdg_stable_dt), then one step as tdg_rk_step.
  * dt_k is written to dt_hist[k] (device, n_steps doubles) and read there by the stage
  * kernels, so the loop needs no host round trip.  U, work: as tdg_rk_step.
+ * dt_hist[k] = 0 reports that the state entering step k had an inadmissible cell mean
+ * (density or pressure not positive, or a value not finite): the run is invalid from that
+ * step on, and since the loop does not synchronise, the caller checks dt_hist afterwards.
  * Errors: TDG_ERR_INVALID_ARG (null pointers, cfl <= 0, n_steps < 0). */
 int tdg_rk_step_adaptive(tdg_ctx* ctx, void* U, void* work, double cfl, int n_steps, double* dt_hist,
                          void* hip_stream);
@@ -231,8 +245,11 @@ int tdg_residual_vjp_axpy(tdg_ctx* ctx, const void* U, const void* W, double c, 
 
 /* Admissibility of internal state U: the number of elements where, at some volume
  * quadrature point, a conserved variable is not finite or the density or pressure is not
- * positive (n_bad: device int64, overwritten).  A run's failure detector: call it every
- * few steps and stop when it is non-zero. */
+ * positive (n_bad: device int64, overwritten).  The pressure is the one of the equation of
+ * state with the energy relation of Sec. II.A (eq. 4 and the energy definition after it);
+ * the flux Jacobian's sound speed sqrt(gamma p / rho) of Sec. II.B needs both positive.
+ * A run's failure detector: call it every few steps and stop when it is non-zero.
+ * Errors: TDG_ERR_INVALID_ARG (NULL), TDG_ERR_STATE, TDG_ERR_HIP. */
 int tdg_check_state(tdg_ctx* ctx, const void* U, int64_t* n_bad, void* hip_stream);
 
 /* Integrated slip-wall pressure J = sum over slip-wall faces of int_f p(U-) dA (boundary-face
@@ -244,7 +261,8 @@ int tdg_wall_pressure(tdg_ctx* ctx, const void* U, double* J, void* dJdU, void* 
 /* Explicit time step as the global minimum of local steps (the paper's minimum over the
  * local time steps of all cells, Sec. III.C, computed by a GPU reduction):
  *   dt = min_K cfl d_K / ((2p+1)(|u_K| + c_K)),  d_K = 6|K| / sum_f A_f,
- * with u_K, c_K from the cell means of U.  dt: device double, overwritten. */
+ * with u_K, c_K from the cell means of U.  dt: device double, overwritten; 0 when some
+ * cell mean is inadmissible (density or pressure not positive, or a value not finite). */
 int tdg_stable_dt(tdg_ctx* ctx, const void* U, double cfl, double* dt, void* hip_stream);
 
 /* Synchronise the stream; map a pending asynchronous HIP error to TDG_ERR_HIP. */

@@ -599,6 +599,11 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
           for (int v = 0; v < 5; ++v)
             *reinterpret_cast<uint2*>(reinterpret_cast<E1*>(lds_comp) + ((wslot * 16 + col) * 5 + v) * (32 * KS) +
                                       16 * mt + 4 * g) = uint2{0, 0};
+        // the slots read below were written by other lanes of this wave: order the LDS
+        // writes before the reads (and, after them, the reads before the next group's writes)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         if (live) {
 #pragma unroll
           for (int v = 0; v < 5; ++v)
@@ -607,6 +612,9 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
               reinterpret_cast<Op*>(a.q_out)[(((int64_t)e * 5 + v) * KS + s) * 4 + g] =
                   lds_comp[(((wslot * 16 + col) * 5 + v) * KS + s) * 4 + g];
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
     }
   }

@@ -110,7 +110,7 @@ __global__ void wall_pressure_kernel(MeshView m, int np, int nf, RefView r, doub
 // Global minimum of the local explicit steps dt_K = cfl d_K / ((2p+1)(|u_K| + c_K)) over
 // the cell means, d_K = 6|K| / sum_f A_f (the paper's minimum of local time steps, here a
 // wavefront shuffle reduction per block and one atomic minimum on the bit pattern of a
-// positive double).
+// non-negative double; 0 when some cell mean is inadmissible).
 __global__ void local_dt_kernel(MeshView m, int np, double gamma, double scale, const void* u, int f32,
                                 unsigned long long* out) {
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -136,6 +136,10 @@ __global__ void local_dt_kernel(MeshView m, int np, double gamma, double scale, 
     const double vol = 1.0 / m.inv_vol[e];
     const double d = 12.0 * vol / area2;  // 6 |K| / sum A_f
     dt = scale * d / lam;
+    // an inadmissible cell mean (rho or p not positive, or not finite) gives a NaN, zero or
+    // infinite local step: it becomes 0, so that the minimum reports it (a NaN would be
+    // dropped by the comparisons below and by the atomic minimum on the bit pattern)
+    if (!(dt > 0.0 && dt <= 1.79e308)) dt = 0.0;
   }
   for (int off = 32; off > 0; off >>= 1) {
     const double o = __shfl_down(dt, off, 64);

@@ -178,7 +178,8 @@ class Solver:
                          stream=None) -> torch.Tensor:
         """n SSP-RK3 steps in place on U, each with dt = the device minimum of the local stable
         steps of the current U (no host synchronisation).  Returns the steps taken, a device
-        tensor of n_steps doubles."""
+        tensor of n_steps doubles; an entry 0 marks a step whose state had an inadmissible
+        cell mean (the run is invalid from there on)."""
         self._check_state(U)
         work = self.new_work() if work is None else work
         size = ctypes.c_size_t()
