@@ -75,6 +75,18 @@ __device__ __forceinline__ double prec_rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float prec_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double prec_sqrt(double x) { return sqrt(x); }
 
+// double -> bf16 / fp16 operand through float.  Rounding to float first and then to the
+// operand type equals a single correct rounding (float carries at least 2p + 2 bits of
+// either target), but the compiler folds the two conversions into one double -> 16-bit
+// truncation that it expands into a ten-instruction round-to-odd sequence; the empty asm
+// makes the float opaque, so each step is one conversion instruction.
+template <class E1>
+__device__ __forceinline__ E1 to_operand(double x) {
+  float f = (float)x;
+  asm("" : "+v"(f));
+  return (E1)f;
+}
+
 // ---------------------------------------------------------------- Euler physics
 // The pointwise physics is written with explicit fused multiply-adds and compiled without
 // letting the compiler contract any other product into a sum: every inlined copy of a

@@ -577,7 +577,7 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
               const int mode = 16 * mt + 4 * g + j;
-              h[j] = (E1)(mode > 0 ? float(o[j]) : 0.0f);
+              h[j] = mode > 0 ? to_operand<E1>(o[j]) : (E1)0.0f;
             }
             // modes 16 mt + 4 g .. + 3 of (col, v) into this wave's staging record
             *reinterpret_cast<e4_t*>(reinterpret_cast<E1*>(lds_comp) + ((wslot * 16 + col) * 5 + v) * (32 * KS) +
@@ -643,7 +643,7 @@ __global__ __launch_bounds__(256) void pack_kernel(MeshView m, const double* __r
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int mode = 4 * k + j;
-      h[j] = (E1)((mode > 0 && mode < NP) ? float(x[j]) : 0.0f);
+      h[j] = (mode > 0 && mode < NP) ? to_operand<E1>(x[j]) : (E1)0.0f;
     }
     *reinterpret_cast<e4v_t*>(rec + (el * 5 + v) * REC + 4 * k) = h;
     if (k == 0) c0[v * m.epad + e] = float(x[0]);
