@@ -221,6 +221,17 @@ int tdg_rk_step_adaptive(tdg_ctx* ctx, void* U, void* work, double cfl, int n_st
 /* Bytes of the work buffer tdg_rk_step needs. */
 int tdg_work_bytes(const tdg_ctx* ctx, size_t* bytes);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): tdg_rk_step with the work buffer taken
+ * from a fixed 64 MiB device array of the library (one per GPU, held from the library's
+ * load on that device until the process ends) instead of a caller buffer.  Same kernels and
+ * results as tdg_rk_step; allocates nothing.  The array is shared by every call on a GPU
+ * and keeps the last call's contents (nothing in it needs to start at zero): calls that
+ * overlap in time on one GPU race, so callers serialise them.
+ * Errors: TDG_ERR_NOMEM when tdg_work_bytes() exceeds 64 MiB (e.g. above ~25,000 P3 FP64
+ * elements), checked before any device work; otherwise as tdg_rk_step. */
+int tdg_rk_step_noalloc(tdg_ctx* ctx, void* U, double dt, int n_steps, void* hip_stream);
+
 /* Vector-Jacobian product Ubar = (dR/dU)^T W at U (all internal layout; Ubar overwritten).
  * Element-centric: each element gathers U and W of its neighbours and applies the
  * transposed interpolation, flux Jacobians and transposed lift of its own and its

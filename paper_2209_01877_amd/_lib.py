@@ -45,6 +45,7 @@ _SIGS = {
     "tdg_project": (_i, [_p, _p, _p, _p]),
     "tdg_residual": (_i, [_p, _p, _p, _p]),
     "tdg_rk_step": (_i, [_p, _p, _p, _d, _i, _p]),
+    "tdg_rk_step_noalloc": (_i, [_p, _p, _d, _i, _p]),
     "tdg_rk_step_adaptive": (_i, [_p, _p, _p, _d, _i, _p, _p]),
     "tdg_check_state": (_i, [_p, _p, _p, _p]),
     "tdg_set_viscosity": (_i, [_p, _d, _d]),

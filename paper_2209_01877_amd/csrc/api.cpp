@@ -318,6 +318,11 @@ size_t work_bytes(const tdg_ctx* c) { return 2 * state_bytes(c) + 3 * comp_bytes
 
 }  // namespace
 
+namespace tetdg {
+// Record an error on a context for the entry points defined in other source files.
+int ctx_fail(tdg_ctx* c, int code, const char* msg) { return fail(c, code, msg ? msg : ""); }
+}  // namespace tetdg
+
 extern "C" {
 
 int tdg_create(int order_p, int precision, double gamma, tdg_ctx** out) {

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include "dg_common.hpp"
+#include "tetdg.h"
 
 namespace tetdg {
 
@@ -91,5 +92,7 @@ hipError_t launch_local_dt(int p, int prec, const MeshView& m, double gamma, dou
 hipError_t launch_stream_probe(int kind, const void* src, void* dst, size_t bytes, hipStream_t s);
 hipError_t launch_project(int p, int prec, const MeshView& m, const RefView& r, double gamma, const double* prim,
                           void* internal, hipStream_t s);
+// Set a context's last-error text and return code (entry points outside api.cpp).
+int ctx_fail(::tdg_ctx* c, int code, const char* msg);
 
 }  // namespace tetdg

@@ -174,6 +174,14 @@ class Solver:
               self._ctx, "tdg_rk_step")
         return U
 
+    def rk_step_noalloc(self, U: torch.Tensor, dt: float, n_steps: int = 1, stream=None) -> torch.Tensor:
+        """As rk_step, with the work buffer in the library's fixed per-GPU scratch (allocates
+        nothing; meshes whose work buffer exceeds 64 MiB are refused)."""
+        self._check_state(U)
+        check(lib.tdg_rk_step_noalloc(self._ctx, _ptr(U), float(dt), int(n_steps), _stream(stream)), self._ctx,
+              "tdg_rk_step_noalloc")
+        return U
+
     def rk_step_adaptive(self, U: torch.Tensor, cfl: float, n_steps: int = 1, work: torch.Tensor | None = None,
                          stream=None) -> torch.Tensor:
         """n SSP-RK3 steps in place on U, each with dt = the device minimum of the local stable
