@@ -279,10 +279,17 @@ __device__ __forceinline__ void load_ops(const char* __restrict__ base, uint32_t
     }
 }
 
+template <int P, class Pr>
+constexpr int vjp_min_blocks() {
+  return (!Pr::f64 && P <= 2) ? 2 : 1;
+}
+
 // kRoe selects the face flux at compile time (Roe's adjoint needs more registers).  FP32 up
-// to P2 fits two waves per SIMD; FP64 and higher orders take one.
-template <int P, class Pr, bool kRoe>
-__global__ __launch_bounds__(256, ((!Pr::f64 && P <= 2) ? 2 : 1)) void vjp_kernel(VjpArgs a) {
+// to P2 fits two waves per SIMD; FP64 and higher orders take one.  kLds: the operand tables
+// are copied into LDS once per workgroup (every MFMA A operand is then an LDS read instead
+// of an L1/L2 access); P4 FP64 (320 KB) and P4 FP32 (160 KB) read them from global memory.
+template <int P, class Pr, bool kRoe, bool kLds>
+__global__ __launch_bounds__(256, (vjp_min_blocks<P, Pr>())) void vjp_kernel(VjpArgs a) {
   using O = Ord<P>;
   using V = VjpLayout<P>;
   using S = typename Pr::S;
@@ -292,7 +299,16 @@ __global__ __launch_bounds__(256, ((!Pr::f64 && P <= 2) ? 2 : 1)) void vjp_kerne
   constexpr int NP = O::NP, NQ = O::NQ, NF = O::NF, MT = O::MT, QT = O::QT, FT = O::FT, KS = V::KS;
   static_assert(Pr::KW == 1, "the adjoint uses the f64/f32 instructions");
 
-  const Op* __restrict__ vt = reinterpret_cast<const Op*>(a.tab);
+  __shared__ Op lds_tab[kLds ? V::n_slots * 64 : 1];
+  const Op* __restrict__ vt;
+  if constexpr (kLds) {
+    const Op* src = reinterpret_cast<const Op*>(a.tab);
+    for (int i = threadIdx.x; i < V::n_slots * 64; i += blockDim.x) lds_tab[i] = src[i];
+    __syncthreads();
+    vt = lds_tab;
+  } else {
+    vt = reinterpret_cast<const Op*>(a.tab);
+  }
   const int lane = threadIdx.x & 63, g = lane >> 4, col = lane & 15;
   const char* __restrict__ ubase = reinterpret_cast<const char*>(a.u);
   const char* __restrict__ wbase = reinterpret_cast<const char*>(a.w);
@@ -517,7 +533,10 @@ __global__ __launch_bounds__(256, ((!Pr::f64 && P <= 2) ? 2 : 1)) void vjp_kerne
 
 template <int P, class Pr>
 hipError_t launch_vjp_impl(const VjpArgs& a, hipStream_t stream) {
-  auto kern = a.flux == 1 ? vjp_kernel<P, Pr, true> : vjp_kernel<P, Pr, false>;
+  // tables in LDS when they fit in the share of one workgroup (160 KB per CU over the
+  // workgroups resident per CU)
+  constexpr bool lds = sizeof(typename Pr::Op) * VjpLayout<P>::n_slots * 64 <= 160 * 1024 / vjp_min_blocks<P, Pr>();
+  auto kern = a.flux == 1 ? vjp_kernel<P, Pr, true, lds> : vjp_kernel<P, Pr, false, lds>;
   int per_cu = 0;
   hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0);
   if (err != hipSuccess) return err;
