@@ -73,6 +73,11 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
   // mixed modes: per-wave staging of the operand companion written by the epilogue, so
   // that each element's record leaves as whole 16-byte slots (16 elements x 5 x KS x 4)
   __shared__ Op lds_comp[Pr::mixed ? 4 * 16 * 5 * KS * 4 : 1];
+  // mixed modes: per-wave exchange of the cell-mean face data.  The four lane groups of a
+  // column hold the same element, so lane group g evaluates face g's mean flux, neighbour
+  // mean and normal once, and every lane reads face f's record here (16 floats per lane:
+  // neighbour / ghost mean 5, mean flux 5, N 3, |N| 1, padding 2)
+  __shared__ float lds_face[Pr::mixed ? 4 * 64 * 16 : 1];
   const Op* __restrict__ tab;
   if constexpr (kLds) {
     const Op* src = reinterpret_cast<const Op*>(a.tab);
@@ -163,8 +168,8 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
         for (int v = 0; v < 5; ++v) {
 #pragma unroll
           for (int s = 0; s < KS; ++s) bx[v][s] = q[(((int64_t)en * 5 + v) * KS + s) * 4 + g];
-          cx[v] = a.c0_in[v * epad + en];
         }
+        (void)cx;
       } else {
         load_operands<Pr, NP, KS>(ubase, var_bytes, (uint32_t)en * 4 * sizeof(S), om, bx);
       }
@@ -172,7 +177,15 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
     Op bn[5][KS];
     T c0n[5];
     load_nbr(0, bn, c0n);
-    if constexpr (Pr::mixed) contra_flux<T>(c0t, Mt, gm1, ybar);
+    // mixed: lane group g's face (face g): the neighbour's cell mean (its load is issued here
+    // and consumed after the volume integral)
+    const int nbg = g == 0 ? nbr[0] : g == 1 ? nbr[1] : g == 2 ? nbr[2] : nbr[3];
+    T cmg[5];
+    if constexpr (Pr::mixed) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) cmg[v] = a.c0_in[v * epad + (nbg >= 0 ? nbg : e)];
+      contra_flux<T>(c0t, Mt, gm1, ybar);
+    }
 
     Acc acc[MT][5];
 #pragma unroll
@@ -258,24 +271,51 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
     }
 
     // ------------------------------------------------------------ face integrals
+    if constexpr (Pr::mixed) {
+      // face g of this lane's element: normal, neighbour (or ghost) mean and the mean flux,
+      // staged for the whole wave (the fence orders these writes after the previous group's
+      // reads of the same slots)
+      T Ng[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        Ng[c] = g == 0 ? (Mt[c] + Mt[3 + c] + Mt[6 + c]) : g == 1 ? -Mt[c] : g == 2 ? -Mt[3 + c] : -Mt[6 + c];
+      const T nng = sqrt(Ng[0] * Ng[0] + Ng[1] * Ng[1] + Ng[2] * Ng[2]);
+      if (nbg < 0) ghost_state<T>(-nbg, c0t, Ng, far, cmg);
+      T fhg[5];
+      num_flux<kRoe, T>(c0t, cmg, Ng, nng, gamma, fhg);
+      typedef float f4v_t __attribute__((ext_vector_type(4)));
+      f4v_t* slot = reinterpret_cast<f4v_t*>(lds_face + (wslot * 64 + lane) * 16);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      slot[0] = f4v_t{cmg[0], cmg[1], cmg[2], cmg[3]};
+      slot[1] = f4v_t{cmg[4], fhg[0], fhg[1], fhg[2]};
+      slot[2] = f4v_t{fhg[3], fhg[4], Ng[0], Ng[1]};
+      slot[3] = f4v_t{Ng[2], nng, 0.0f, 0.0f};
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
 #pragma unroll 1
     for (int f = 0; f < 4; ++f) {
       T c0nn[5];
       T N[3];
-      if constexpr (Pr::mixed) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-          N[c] = f == 0 ? (Mt[c] + Mt[3 + c] + Mt[6 + c]) : f == 1 ? -Mt[c] : f == 2 ? -Mt[3 + c] : -Mt[6 + c];
-      } else {
-        face_normal<T>(f, Md, N);
-      }
-      const T nn = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+      T nn;
       const int nbf = f == 0 ? nbr[0] : f == 1 ? nbr[1] : f == 2 ? nbr[2] : nbr[3];
       const int fpl = (fcode >> (2 * f)) & 3;
       T fhbar[5];
       if constexpr (Pr::mixed) {
-        if (nbf < 0) ghost_state<T>(-nbf, c0t, N, far, c0n);
-        num_flux<kRoe, T>(c0t, c0n, N, nn, gamma, fhbar);
+        // face f's record, written by lane group f of this column
+        typedef float f4v_t __attribute__((ext_vector_type(4)));
+        const f4v_t* slot = reinterpret_cast<const f4v_t*>(lds_face + (wslot * 64 + 16 * f + col) * 16);
+        const f4v_t r0 = slot[0], r1 = slot[1], r2 = slot[2], r3 = slot[3];
+        c0n[0] = r0[0], c0n[1] = r0[1], c0n[2] = r0[2], c0n[3] = r0[3], c0n[4] = r1[0];
+        fhbar[0] = r1[1], fhbar[1] = r1[2], fhbar[2] = r1[3], fhbar[3] = r2[0], fhbar[4] = r2[1];
+        N[0] = r2[2], N[1] = r2[3], N[2] = r3[0];
+        nn = r3[1];
+      } else {
+        face_normal<T>(f, Md, N);
+        nn = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
       }
 #pragma unroll 1
       for (int ft = 0; ft < FT; ++ft) {
@@ -378,10 +418,7 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
           }
         }
       }
-      if (f < 3) {
-#pragma unroll
-        for (int v = 0; v < 5; ++v) c0n[v] = c0nn[v];
-      }
+      (void)c0nn;
     }
 
     // ------------------------------------------------------------ epilogue
@@ -683,9 +720,10 @@ template <int P, class Pr>
 static hipError_t launch_stage_impl(const StageArgs& a, hipStream_t stream) {
   using L = Layout<P, Pr::KW>;
   constexpr size_t tab_bytes = sizeof(typename Pr::Op) * L::n_slots * 64;
-  // stage the tables in LDS when they fit beside the companion staging area in the LDS
-  // share of one workgroup (160 KB per CU over the workgroups resident per CU)
-  constexpr size_t comp_bytes = Pr::mixed ? sizeof(typename Pr::Op) * 4 * 16 * 5 * L::KS * 4 : 0;
+  // stage the tables in LDS when they fit beside the companion staging and face-record
+  // areas in the LDS share of one workgroup (160 KB per CU over the workgroups resident per CU)
+  constexpr size_t comp_bytes =
+      Pr::mixed ? sizeof(typename Pr::Op) * 4 * 16 * 5 * L::KS * 4 + sizeof(float) * 4 * 64 * 16 : 0;
   constexpr bool lds = tab_bytes + comp_bytes <= 160 * 1024 / stage_min_blocks<P, Pr>();
   auto kern = a.flux == 1 ? stage_kernel<P, Pr, lds, true> : stage_kernel<P, Pr, lds, false>;
   int per_cu = 0;
