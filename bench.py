@@ -5,14 +5,16 @@ the periodic [0,10]^3 cube split into 64^3 hexahedra x 6 = 1,572,864 tets, P3 (2
 5 variables: 157,286,400 DOF), element order shuffled from a seed and renumbered along a
 Hilbert curve.  One step = one SSP-RK3 step = three fused residual+update launches.
 
-The headline value is the mixed bf16 path (bf16 MFMA contractions with fp32 accumulation,
-fp32 fluxes, fp64 state); the same workload is also timed in fp32, fp16-mixed and fp64, the
-residual entry point is timed, and each precision's state after the timed steps is compared
-with the fp64 GPU result (relative L2 per variable).  cpu_baseline is the FP64 CPU oracle on
-a 28^3 x 6 sample of the same problem (all host threads; one thread on a 14^3 x 6 sample).
-stream_ceiling is the practical bandwidth of the box; the extra workloads (--extras) are P4,
-the adjoint, the viscous terms, Roe's flux, temporal mixed precision and graph replay
-on the smallest mesh.
+The headline value is the mixed fp16 path (fp16 MFMA contractions with fp32 accumulation,
+fp32 fluxes, fp64 state); the same workload is also timed in fp32, bf16-mixed and fp64, the
+residual entry point is timed, and each precision's result is compared with the fp64 GPU
+result: the state after the timed steps (relative to the whole state and to the increment)
+and one residual of the initial state.  cpu_baseline is the FP64 CPU oracle at the 48^3 x 6
+size (all host threads: one residual by dual-phase timing and one SSP-RK3 step; one thread on
+a 14^3 x 6 sample).  stream_ceiling is the practical bandwidth of the box; counters are the
+committed shader-counter summary of the stage kernel (when its sources are unchanged); the
+extra workloads (--extras) are P4, the adjoint, the viscous terms, Roe's flux, temporal mixed
+precision, graph replay on the smallest mesh and the element-renumbering ablation.
 """
 from __future__ import annotations
 
@@ -59,6 +61,29 @@ def measured_traffic(precision: str):
         return None
     r = d["per_precision"][precision]
     return (r["fetch_kib_per_dispatch"] * d["copy_fetch_factor"] + r["write_kib_per_dispatch"] * d["copy_write_factor"]) * 1024.0
+
+
+def measured_counters():
+    """Per precision, the stage kernel's MFMA utilisation, VALU busy fraction, L2 hit rate and
+    wave wait fraction from the committed counter summary (rocprofv3 passes over the same
+    benchmark; MFMA utilisation = SQ_VALU_MFMA_BUSY_CYCLES over the SIMD-cycles of the
+    dispatch, 32 x SQ_CYCLES), or None when the kernel sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("source_sha256") != kernel_source_hash():
+        return None
+    out = {}
+    for prec, r in d.get("per_precision", {}).items():
+        if "mfma_util" in r:
+            out[prec] = {k: r[k] for k in ("mfma_util", "valu_busy", "wait_frac", "tcc_hit_rate", "avg_kernel_us")
+                         if k in r}
+    return {"per_precision": out, "source": os.path.relpath(TRAFFIC_FILE, ROOT),
+            "definition": "mfma_util = SQ_VALU_MFMA_BUSY_CYCLES / (32 SQ_CYCLES); valu_busy = 4 SQ_ACTIVE_INST_VALU / "
+                          "(32 SQ_CYCLES); wait_frac = SQ_WAIT_ANY / SQ_WAVE_CYCLES; tcc_hit_rate = TCC_HIT / "
+                          "(TCC_HIT + TCC_MISS)"} if out else None
 
 
 def stage_flops(p: int) -> float:
@@ -583,7 +608,9 @@ def main():
     ap.add_argument("--n", type=int, default=64, help="hexahedra per cube edge")
     ap.add_argument("--p", type=int, default=3)
     ap.add_argument("--renumber", default="hilbert")
-    ap.add_argument("--precisions", default="bf16,fp32,fp16,fp64")
+    ap.add_argument("--precisions", default="fp16,fp32,bf16,fp64",
+                    help="the first is the headline (the mixed mode with fp16 operands: as fast as bf16 and "
+                         "eight times more accurate on this path)")
     ap.add_argument("--cpu-n", type=int, default=48, help="oracle sample: hexahedra per edge (48: the C2 size)")
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
@@ -653,6 +680,7 @@ def main():
             "changed); residual_rel_l2_vs_fp64 = |R - R_fp64| / |R_fp64| for one residual of the initial state, "
             "per variable against that variable's norm"),
     }
+    line["counters"] = measured_counters()
     # the same stage against the box's practical bandwidth (a tuned streaming copy)
     stage_s = r["ms_per_step"] / 3.0 / 1e3
     traffic = line["roofline"]["traffic"]

@@ -137,9 +137,27 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
     double Md[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) Md[i] = mv.M[i * epad + e];
+    // Mixed modes: the pointwise deviation fluxes (volume and face) are linear in M and in
+    // the face normals built from it, and M = |det J| J^-1 scales as h^2, so on small
+    // elements they would fall below the normal range of fp16 operands.  They are computed
+    // with M scaled by a power of two (largest entry in [0.5, 1)), which changes no fp32
+    // rounding, and the contractions' fp32 results are scaled back exactly in the epilogue.
+    double unscale = 1.0;
     T Mt[9];
+    if constexpr (Pr::mixed) {
+      double mx = 0.0;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) Mt[i] = T(Md[i]);
+      for (int i = 0; i < 9; ++i) mx = fmax(mx, fabs(Md[i]));
+      int ex = 0;
+      (void)frexp(mx, &ex);
+      unscale = ldexp(1.0, ex);
+      const double sc = ldexp(1.0, -ex);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) Mt[i] = T(Md[i] * sc);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) Mt[i] = T(Md[i]);
+    }
     const int fcode = mv.fcode[e];
     int nbr[4];
 #pragma unroll
@@ -580,7 +598,7 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int mode = 16 * mt + drow_of<Pr>(g, j);
-          double r = double(acc[mt][v][j]);
+          double r = double(acc[mt][v][j]) * unscale;
           if constexpr (Pr::mixed) r += mean[j];
           r *= ivol;
           r += radd[v][j];

@@ -357,6 +357,33 @@ def test_rk_step_mixed_multistep(p, prec):
     assert_parity(dg, got - U, got64 - U, tol, 3 * tol, label=f"p={p} {prec} 3 steps, increment vs GPU FP64")
 
 
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_mixed_residual_scales_exactly_with_the_mesh(prec):
+    """The deviation fluxes are linear in M = |det J| J^-1, which scales as h^2: on a mesh
+    shrunk by 2^-10 they would sit far below fp16's normal range (smallest normal 6.1e-5)
+    and be lost in the operand conversion.  The kernel scales M per element by a power of
+    two before the fp32 fluxes and undoes it exactly on the fp32 contraction results, so the
+    mixed residual of the shrunk mesh is bit for bit 2^10 times that of the unit mesh (the
+    geometry scales exactly by powers of two), in bf16 and in fp16; the error against the
+    GPU FP64 residual (itself oracle-checked) is the stated one."""
+    import dataclasses
+
+    base = make_mesh("jitter4")
+    R = {}
+    for k in (0, 10):
+        mesh = dataclasses.replace(base, elem_xyz=base.elem_xyz * 2.0 ** -k)
+        dg = oracle(2, mesh)
+        U = random_state(dg, seed=13)
+        R[k] = gpu_residual(solver(2, prec, mesh), U)
+        if k == 0:
+            R64 = gpu_residual(solver(2, "fp64", mesh), U)
+            err = float(((R[k] - R64).pow(2).sum() / R64.pow(2).sum()).sqrt())
+    print(f"{prec}: residual error vs FP64 {err:.3e}; shrunk mesh max |R - 2^10 R_unit| "
+          f"{float((R[10] - R[0] * 2.0 ** 10).abs().max()):.3e}")
+    assert err < {"bf16": 5e-2, "fp16": 1e-2}[prec]
+    assert torch.equal(R[10], R[0] * 2.0 ** 10)
+
+
 def test_hundred_rk_steps_p3():
     """Full-length run: P3 isentropic vortex on the shuffled periodic 12^3 x 6 cube (10,368
     tets, Hilbert order), 100 SSP-RK3 steps at CFL 0.2.  FP64 against the oracle to 1e-12;
