@@ -71,13 +71,18 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
 
   __shared__ Op lds_tab[kLds ? L::n_slots * 64 : 1];
   // mixed modes: per-wave staging of the operand companion written by the epilogue, so
-  // that each element's record leaves as whole 16-byte slots (16 elements x 5 x KS x 4)
-  __shared__ Op lds_comp[Pr::mixed ? 4 * 16 * 5 * KS * 4 : 1];
+  // that each element's record leaves as whole 16-byte slots.  An element's record (5 x
+  // 32 KS operand values) is followed by 8 padding values, so that the 16 columns' records
+  // start in different LDS banks (a 320-byte stride put four columns on each bank group).
+  constexpr int CES = 5 * 32 * KS + 8;  // record stride, operand values
+  __shared__ Op lds_comp[Pr::mixed ? 4 * 16 * CES / 8 : 1];
   // mixed modes: per-wave exchange of the cell-mean face data.  The four lane groups of a
   // column hold the same element, so lane group g evaluates face g's mean flux, neighbour
-  // mean and normal once, and every lane reads face f's record here (16 floats per lane:
-  // neighbour / ghost mean 5, mean flux 5, N 3, |N| 1, padding 2)
-  __shared__ float lds_face[Pr::mixed ? 4 * 64 * 16 : 1];
+  // mean and normal once, and every lane reads face f's record here: 7 float pairs
+  // (neighbour / ghost mean 5, mean flux 5, N 3, |N| 1), pair-major so that the lanes of a
+  // wave access consecutive 8-byte words
+  typedef float f2v_t __attribute__((ext_vector_type(2)));
+  __shared__ f2v_t lds_face[Pr::mixed ? 7 * 4 * 64 : 1];
   const Op* __restrict__ tab;
   if constexpr (kLds) {
     const Op* src = reinterpret_cast<const Op*>(a.tab);
@@ -301,15 +306,17 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
       if (nbg < 0) ghost_state<T>(-nbg, c0t, Ng, far, cmg);
       T fhg[5];
       num_flux<kRoe, T>(c0t, cmg, Ng, nng, gamma, fhg);
-      typedef float f4v_t __attribute__((ext_vector_type(4)));
-      f4v_t* slot = reinterpret_cast<f4v_t*>(lds_face + (wslot * 64 + lane) * 16);
+      f2v_t* slot = lds_face + wslot * 64 + lane;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      slot[0] = f4v_t{cmg[0], cmg[1], cmg[2], cmg[3]};
-      slot[1] = f4v_t{cmg[4], fhg[0], fhg[1], fhg[2]};
-      slot[2] = f4v_t{fhg[3], fhg[4], Ng[0], Ng[1]};
-      slot[3] = f4v_t{Ng[2], nng, 0.0f, 0.0f};
+      slot[0 * 256] = f2v_t{cmg[0], cmg[1]};
+      slot[1 * 256] = f2v_t{cmg[2], cmg[3]};
+      slot[2 * 256] = f2v_t{cmg[4], fhg[0]};
+      slot[3 * 256] = f2v_t{fhg[1], fhg[2]};
+      slot[4 * 256] = f2v_t{fhg[3], fhg[4]};
+      slot[5 * 256] = f2v_t{Ng[0], Ng[1]};
+      slot[6 * 256] = f2v_t{Ng[2], nng};
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -324,13 +331,13 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
       T fhbar[5];
       if constexpr (Pr::mixed) {
         // face f's record, written by lane group f of this column
-        typedef float f4v_t __attribute__((ext_vector_type(4)));
-        const f4v_t* slot = reinterpret_cast<const f4v_t*>(lds_face + (wslot * 64 + 16 * f + col) * 16);
-        const f4v_t r0 = slot[0], r1 = slot[1], r2 = slot[2], r3 = slot[3];
-        c0n[0] = r0[0], c0n[1] = r0[1], c0n[2] = r0[2], c0n[3] = r0[3], c0n[4] = r1[0];
-        fhbar[0] = r1[1], fhbar[1] = r1[2], fhbar[2] = r1[3], fhbar[3] = r2[0], fhbar[4] = r2[1];
-        N[0] = r2[2], N[1] = r2[3], N[2] = r3[0];
-        nn = r3[1];
+        const f2v_t* slot = lds_face + wslot * 64 + 16 * f + col;
+        const f2v_t r0 = slot[0 * 256], r1 = slot[1 * 256], r2 = slot[2 * 256], r3 = slot[3 * 256],
+                    r4 = slot[4 * 256], r5 = slot[5 * 256], r6 = slot[6 * 256];
+        c0n[0] = r0[0], c0n[1] = r0[1], c0n[2] = r1[0], c0n[3] = r1[1], c0n[4] = r2[0];
+        fhbar[0] = r2[1], fhbar[1] = r3[0], fhbar[2] = r3[1], fhbar[3] = r4[0], fhbar[4] = r4[1];
+        N[0] = r5[0], N[1] = r5[1], N[2] = r6[0];
+        nn = r6[1];
       } else {
         face_normal<T>(f, Md, N);
         nn = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
@@ -635,7 +642,7 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
               h[j] = mode > 0 ? to_operand<E1>(o[j]) : (E1)0.0f;
             }
             // modes 16 mt + 4 g .. + 3 of (col, v) into this wave's staging record
-            *reinterpret_cast<e4_t*>(reinterpret_cast<E1*>(lds_comp) + ((wslot * 16 + col) * 5 + v) * (32 * KS) +
+            *reinterpret_cast<e4_t*>(reinterpret_cast<E1*>(lds_comp) + (wslot * 16 + col) * CES + v * (32 * KS) +
                                      16 * mt + 4 * g) = h;
             if (mt == 0 && g == 0) a.c0_out[v * epad + e] = float(o[0]);
           }
@@ -652,7 +659,7 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
         for (int mt = MT; mt < 2 * KS; ++mt)
 #pragma unroll
           for (int v = 0; v < 5; ++v)
-            *reinterpret_cast<uint2*>(reinterpret_cast<E1*>(lds_comp) + ((wslot * 16 + col) * 5 + v) * (32 * KS) +
+            *reinterpret_cast<uint2*>(reinterpret_cast<E1*>(lds_comp) + (wslot * 16 + col) * CES + v * (32 * KS) +
                                       16 * mt + 4 * g) = uint2{0, 0};
         // the slots read below were written by other lanes of this wave: order the LDS
         // writes before the reads (and, after them, the reads before the next group's writes)
@@ -665,7 +672,7 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
 #pragma unroll
             for (int s = 0; s < KS; ++s)
               reinterpret_cast<Op*>(a.q_out)[(((int64_t)e * 5 + v) * KS + s) * 4 + g] =
-                  lds_comp[(((wslot * 16 + col) * 5 + v) * KS + s) * 4 + g];
+                  lds_comp[(wslot * 16 + col) * (CES / 8) + (v * KS + s) * 4 + g];
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -741,7 +748,7 @@ static hipError_t launch_stage_impl(const StageArgs& a, hipStream_t stream) {
   // stage the tables in LDS when they fit beside the companion staging and face-record
   // areas in the LDS share of one workgroup (160 KB per CU over the workgroups resident per CU)
   constexpr size_t comp_bytes =
-      Pr::mixed ? sizeof(typename Pr::Op) * 4 * 16 * 5 * L::KS * 4 + sizeof(float) * 4 * 64 * 16 : 0;
+      Pr::mixed ? sizeof(typename Pr::Op) / 8 * 4 * 16 * (5 * 32 * L::KS + 8) + 2 * sizeof(float) * 7 * 4 * 64 : 0;
   constexpr bool lds = tab_bytes + comp_bytes <= 160 * 1024 / stage_min_blocks<P, Pr>();
   auto kern = a.flux == 1 ? stage_kernel<P, Pr, lds, true> : stage_kernel<P, Pr, lds, false>;
   int per_cu = 0;
