@@ -108,7 +108,13 @@ void pack_stage(const RefElem& R, int prec, std::vector<unsigned char>& out) {
   // (4x4x1 block operands in fp32; in fp64 lanes 16 g + 0..3 hold the four values of lane
   // group g's point; the stage kernel's kTail4)
   const bool tail4 = !mixed && NP - 16 * (O::MT - 1) <= 4;
-  auto tile_mode = [&](int mt, int r) { return 16 * mt + ((tail4 && mt == O::MT - 1) ? r % 4 : r); };
+  // mixed, P3 / P4: last mode tile of at most 4 modes spread over the lane groups, row 4 g
+  // holding mode 16 mt + g and the other rows zero (the stage kernel's kSpread)
+  const bool spread = mixed && O::MT >= 2 && NP - 16 * (O::MT - 1) <= 4;
+  auto tile_mode = [&](int mt, int r) {
+    if (spread && mt == O::MT - 1) return r % 4 == 0 ? 16 * mt + r / 4 : NP;
+    return 16 * mt + ((tail4 && mt == O::MT - 1) ? r % 4 : r);
+  };
   // interp
   for (int qt = 0; qt < O::QT; ++qt)
     for (int s = 0; s < KS; ++s)
@@ -252,12 +258,15 @@ void build_tables(tdg_ctx* c) {
   // fp64 accumulator element j of lane group g is the same mode as in the fp32 accumulators.
   // k = 0..2: volume moments (+); k = 3: face 0; k = 4..6: faces 1..3 (face moments negated).
   const int MT = (NP + 15) / 16;
+  // the last tile of at most 4 modes (P3, P4): row r < 4 holds mode 16 mt + r (register 0 of
+  // lane group r), as in the spread fp32 tables
+  const bool spread = MT >= 2 && NP - 16 * (MT - 1) <= 4;
   c->mean_tab.assign((size_t)MT * 2 * 64, 0.0);
   for (int mt = 0; mt < MT; ++mt)
     for (int step = 0; step < 2; ++step)
       for (int l = 0; l < 64; ++l) {
         const int r = l % 16, k = 4 * step + l / 16;
-        const int mode = 16 * mt + 4 * (r % 4) + r / 4;
+        const int mode = (spread && mt == MT - 1) ? (r < 4 ? 16 * mt + r : NP) : 16 * mt + 4 * (r % 4) + r / 4;
         double v = 0.0;
         if (mode < NP && k < 7) {
           const int face = k == 3 ? 0 : k - 3;

@@ -59,7 +59,9 @@ constexpr int stage_min_blocks() {
 
 // kLds: reference tables staged in LDS; kRoe: Roe's interface flux instead of Rusanov's
 // (a compile-time choice keeps the other flux's code and registers out of the kernel).
-template <int P, class Pr, bool kLds, bool kRoe>
+// kResid (mixed modes only): the residual without the RK update, a compile-time choice so
+// that the epilogue's state reads sit in no branch.
+template <int P, class Pr, bool kLds, bool kRoe, bool kResid>
 __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel(StageArgs a) {
   using O = Ord<P>;
   using L = Layout<P, Pr::KW>;
@@ -95,6 +97,15 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
 
   const int lane = threadIdx.x & 63, g = lane >> 4, col = lane & 15;
   const int wslot = threadIdx.x >> 6;  // wavefront within the workgroup
+  if constexpr (Pr::mixed) {
+    // the staging records' padding (modes past the last, the slots past the last mode
+    // tile) is never written by the epilogue: zero it once
+    uint32_t* z = reinterpret_cast<uint32_t*>(lds_comp) + wslot * 8 * CES;
+    for (int i = lane; i < 8 * CES; i += 64) z[i] = 0u;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
   const char* __restrict__ ubase = reinterpret_cast<const char*>(a.u_in);
   const MeshView& mv = a.mesh;
   const int64_t epad = mv.epad;
@@ -106,6 +117,11 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
   // values read once per lane group — and the four shares are summed across lane groups
   // before the epilogue.
   constexpr bool kTail4 = Pr::KW == 1 && NP - 16 * (MT - 1) <= 4;
+  // Mixed modes, P3 and P4: the last mode tile holds at most 4 modes.  Its table rows put
+  // mode 16 (MT - 1) + g in register 0 of lane group g (fp32 accumulator row 4 g, fp64
+  // accumulator row g) and zeros elsewhere, so that the epilogue handles that tile as one
+  // value per lane, all lanes busy.
+  constexpr bool kSpread = Pr::mixed && MT >= 2 && NP - 16 * (MT - 1) <= 4;
   const uint32_t quad_bytes = (uint32_t)(epad * 4 * sizeof(S));  // one (variable, mode quad) plane
   const uint32_t var_bytes = quad_bytes * NPQ;
   const T gamma = T(a.gamma), gm1 = T(a.gamma - 1.0);
@@ -485,7 +501,16 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
     double Me[Pr::mixed ? 9 : 1], c0e[Pr::mixed ? 5 : 1], c0g[Pr::mixed ? 5 : 1];
     const int fg = g == 3 ? 0 : g + 1;
     const int ng = fg == 0 ? nbr[0] : fg == 1 ? nbr[1] : fg == 2 ? nbr[2] : nbr[3];
+    // mixed: the mean-flux projection's A operands of every tile, requested before the
+    // state values (loads complete in order, so waiting for them then leaves the state
+    // reads in flight)
+    double mtab[Pr::mixed ? MT : 1][2];
     if constexpr (Pr::mixed) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        mtab[mt][0] = a.mean_tab[(uint32_t)((2 * mt) * 64 + lane)];
+        mtab[mt][1] = a.mean_tab[(uint32_t)((2 * mt + 1) * 64 + lane)];
+      }
 #pragma unroll
       for (int i = 0; i < 9; ++i) Me[i] = mv.M[i * epad + e];
       const uint32_t goff = (uint32_t)(ng >= 0 ? ng : e) * 4 * sizeof(S);
@@ -499,12 +524,41 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
     // layout they form one mode quad per lane (one vector access); with the fp64 layout
     // they sit at position g of four quads.  Padding modes of the last quad are written 0.
     double uin[5][4], u0v[5][4], radd[5][4];
+    // kSpread: the last tile's values, one per lane (mode 16 (MT - 1) + g at position g of
+    // quad 4 (MT - 1)), requested together with those of the tile before it
+    double tin[kSpread ? 5 : 1], t0v[kSpread ? 5 : 1];
+    // a per-lane 32-bit byte offset, kept opaque so that the compiler adds it to the uniform
+    // base at the access (one register) instead of keeping 64-bit per-lane addresses
+    // across the group loop
+    auto lane_off = [](uint32_t x) {
+      asm("" : "+v"(x));
+      return x;
+    };
+    // Mixed modes (kFlat): the state reads and the stores of the result are unconditional.
+    // Loads inside lane-dependent or uniform branches keep the compiler from counting the
+    // outstanding loads across the branch, so that every later wait also waits for them.
+    // Padding elements (e >= n_elem, inside the padded arrays) read valid memory and store
+    // zeros; stage 1 (alpha = 0) reads U_in in place of U0 and multiplies it by zero.
+    constexpr bool kFlat = Pr::mixed;
+    const bool rk = Pr::mixed ? !kResid : a.rk != 0;
+    const char* const u0src = a.alpha != 0.0 ? u0base : ubase;
+    auto load_tail = [&]() {
+#pragma unroll
+      for (int v = 0; v < (kSpread ? 5 : 1); ++v) tin[v] = t0v[v] = 0.0;
+      if (!rk) return;
+#pragma unroll
+      for (int v = 0; v < (kSpread ? 5 : 1); ++v) {
+        const uint32_t o = lane_off(eoff + (uint32_t)(4 * (MT - 1)) * quad_bytes + (uint32_t)g * sizeof(S));
+        tin[v] = double(*reinterpret_cast<const S*>(ubase + (size_t)v * var_bytes + o));
+        t0v[v] = double(*reinterpret_cast<const S*>(u0src + (size_t)v * var_bytes + o));
+      }
+    };
     auto load_tile = [&](int mt) {
 #pragma unroll
       for (int v = 0; v < 5; ++v)
 #pragma unroll
         for (int j = 0; j < 4; ++j) uin[v][j] = u0v[v][j] = radd[v][j] = 0.0;
-      if (!live) return;
+      if (!kFlat && !live) return;
       if constexpr (!Pr::mixed) {
         // an added residual part (the viscous terms) in the state's layout and precision
         if (a.r_add) {
@@ -520,18 +574,32 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
             }
         }
       }
-      if (!a.rk) return;
+      if (!rk) return;
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
-        const size_t vo = (size_t)v * var_bytes + eoff;
-        if constexpr (!Pr::f64) {
+        // uniform base of the variable + a 32-bit per-lane offset (one register, and the
+        // loads' scalar-base addressing form)
+        const size_t vb = (size_t)v * var_bytes;
+        if constexpr (kFlat) {
+          // quads past the last read the last one and count as zero
+          const int qd = 4 * mt + g;
+          const uint32_t o = lane_off(eoff + (uint32_t)(qd < NPQ ? qd : NPQ - 1) * quad_bytes);
+          const s4_t x = *reinterpret_cast<const s4_t*>(ubase + vb + o);
+          const s4_t y = *reinterpret_cast<const s4_t*>(u0src + vb + o);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            uin[v][j] = qd < NPQ ? double(x[j]) : 0.0;
+            u0v[v][j] = qd < NPQ ? double(y[j]) : 0.0;
+          }
+        } else if constexpr (!Pr::f64) {
           const int qd = 4 * mt + g;
           if (qd < NPQ) {
-            const s4_t x = *reinterpret_cast<const s4_t*>(ubase + vo + (size_t)qd * quad_bytes);
+            const size_t o = vb + eoff + (size_t)qd * quad_bytes;
+            const s4_t x = *reinterpret_cast<const s4_t*>(ubase + o);
 #pragma unroll
             for (int j = 0; j < 4; ++j) uin[v][j] = double(x[j]);
             if (a.alpha != 0.0) {
-              const s4_t y = *reinterpret_cast<const s4_t*>(u0base + vo + (size_t)qd * quad_bytes);
+              const s4_t y = *reinterpret_cast<const s4_t*>(u0base + o);
 #pragma unroll
               for (int j = 0; j < 4; ++j) u0v[v][j] = double(y[j]);
             }
@@ -541,7 +609,7 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
           for (int j = 0; j < 4; ++j) {
             const int qd = 4 * mt + j;
             if (qd < NPQ) {
-              const size_t o = vo + (size_t)qd * quad_bytes + (size_t)g * sizeof(S);
+              const size_t o = vb + eoff + (size_t)qd * quad_bytes + (size_t)g * sizeof(S);
               uin[v][j] = double(*reinterpret_cast<const S*>(ubase + o));
               if (a.alpha != 0.0) u0v[v][j] = double(*reinterpret_cast<const S*>(u0base + o));
             }
@@ -588,11 +656,12 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
     const double ivol = mv.inv_vol[e];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
-      load_tile(mt);
+      if (!(kSpread && mt == MT - 1)) load_tile(mt);
+      if (kSpread && mt == (MT >= 2 ? MT - 2 : 0)) load_tail();
       double a0 = 0.0, a1 = 0.0;
       if constexpr (Pr::mixed) {
-        a0 = a.mean_tab[(2 * mt) * 64 + lane];
-        a1 = a.mean_tab[(2 * mt + 1) * 64 + lane];
+        a0 = mtab[mt][0];
+        a1 = mtab[mt][1];
       }
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
@@ -601,33 +670,40 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
           mean = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, x0[v], mean, 0, 0, 0);
           mean = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, x1[v], mean, 0, 0, 0);
         }
+        const bool spread = kSpread && mt == MT - 1;
         double o[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int mode = 16 * mt + drow_of<Pr>(g, j);
+          const int mode = spread ? (j == 0 ? 16 * mt + g : NP) : 16 * mt + drow_of<Pr>(g, j);
           double r = double(acc[mt][v][j]) * unscale;
           if constexpr (Pr::mixed) r += mean[j];
           r *= ivol;
           r += radd[v][j];
-          const double out = a.rk ? a.alpha * u0v[v][j] + (1.0 - a.alpha) * (uin[v][j] + dt * r) : r;
-          o[j] = mode < NP ? out : 0.0;
+          const double ui = spread ? tin[kSpread ? v : 0] : uin[v][j];
+          const double u0 = spread ? t0v[kSpread ? v : 0] : u0v[v][j];
+          const double out = rk ? a.alpha * u0 + (1.0 - a.alpha) * (ui + dt * r) : r;
+          o[j] = mode < NP && (!kFlat || live) ? out : 0.0;
         }
-        if (!live) continue;
-        const size_t vo = (size_t)v * var_bytes + eoff;
-        if constexpr (!Pr::f64) {
+        if (!kFlat && !live) continue;
+        char* const ob = obase + (size_t)v * var_bytes;
+        if (spread) {
+          *reinterpret_cast<S*>(ob + lane_off(eoff + (uint32_t)(4 * mt) * quad_bytes + (uint32_t)g * sizeof(S))) = S(o[0]);
+        } else if constexpr (!Pr::f64) {
           const int qd = 4 * mt + g;
           if (qd < NPQ) {
             s4_t x;
 #pragma unroll
             for (int j = 0; j < 4; ++j) x[j] = S(o[j]);
             // streamed out: not read again within this launch
-            __builtin_nontemporal_store(x, reinterpret_cast<s4_t*>(obase + vo + (size_t)qd * quad_bytes));
+            s4_t* dst = kFlat ? reinterpret_cast<s4_t*>(ob + lane_off(eoff + (uint32_t)qd * quad_bytes))
+                              : reinterpret_cast<s4_t*>(ob + eoff + (size_t)qd * quad_bytes);
+            __builtin_nontemporal_store(x, dst);
           }
         } else {
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             const int qd = 4 * mt + j;
-            if (qd < NPQ) *reinterpret_cast<S*>(obase + vo + (size_t)qd * quad_bytes + (size_t)g * sizeof(S)) = o[j];
+            if (qd < NPQ) *reinterpret_cast<S*>(ob + eoff + (size_t)qd * quad_bytes + (size_t)g * sizeof(S)) = o[j];
           }
         }
         if constexpr (Pr::mixed) {
@@ -635,15 +711,21 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
             // operand companion of the result: modes 1.. in the operand precision, mean in fp32
             using E1 = typename Pr::E1;
             typedef E1 e4_t __attribute__((ext_vector_type(4)));
-            e4_t h;
+            E1* rec = reinterpret_cast<E1*>(lds_comp) + (wslot * 16 + col) * CES + v * (32 * KS) + 16 * mt;
+            if (spread) {
+              // mode 16 mt + g from every lane group (modes 16 mt + 4 .. 15 are padding, zero
+              // since the kernel's start)
+              rec[g] = to_operand<E1>(o[0]);
+            } else {
+              e4_t h;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              const int mode = 16 * mt + 4 * g + j;
-              h[j] = mode > 0 ? to_operand<E1>(o[j]) : (E1)0.0f;
+              for (int j = 0; j < 4; ++j) {
+                const int mode = 16 * mt + 4 * g + j;
+                h[j] = mode > 0 ? to_operand<E1>(o[j]) : (E1)0.0f;
+              }
+              // modes 16 mt + 4 g .. + 3 of (col, v) into this wave's staging record
+              *reinterpret_cast<e4_t*>(rec + 4 * g) = h;
             }
-            // modes 16 mt + 4 g .. + 3 of (col, v) into this wave's staging record
-            *reinterpret_cast<e4_t*>(reinterpret_cast<E1*>(lds_comp) + (wslot * 16 + col) * CES + v * (32 * KS) +
-                                     16 * mt + 4 * g) = h;
             if (mt == 0 && g == 0) a.c0_out[v * epad + e] = float(o[0]);
           }
         }
@@ -651,28 +733,23 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
     }
     if constexpr (Pr::mixed) {
       if (comp) {
-        // slots past the last mode tile are zero; then every lane sends the 16-byte slot it
-        // reads as an MFMA operand (modes 32 s + 8 g .. + 7), so the 4 lanes of a column
-        // write their element's whole record
-        using E1 = typename Pr::E1;
-#pragma unroll
-        for (int mt = MT; mt < 2 * KS; ++mt)
-#pragma unroll
-          for (int v = 0; v < 5; ++v)
-            *reinterpret_cast<uint2*>(reinterpret_cast<E1*>(lds_comp) + (wslot * 16 + col) * CES + v * (32 * KS) +
-                                      16 * mt + 4 * g) = uint2{0, 0};
-        // the slots read below were written by other lanes of this wave: order the LDS
-        // writes before the reads (and, after them, the reads before the next group's writes)
+        // every lane sends the 16-byte slot it reads as an MFMA operand (modes 32 s + 8 g ..
+        // + 7), so the 4 lanes of a column write their element's whole record (its padding
+        // slots zero since the kernel's start).  The slots were written by other lanes of
+        // this wave: order the LDS writes before the reads (and, after them, the reads
+        // before the next group's writes)
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         if (live) {
+          // the element's record, then the lane's 16-byte slot within it
+          Op* qrec = reinterpret_cast<Op*>(a.q_out) + (size_t)e * (5 * KS * 4);
+          asm("" : "+v"(qrec));
 #pragma unroll
           for (int v = 0; v < 5; ++v)
 #pragma unroll
             for (int s = 0; s < KS; ++s)
-              reinterpret_cast<Op*>(a.q_out)[(((int64_t)e * 5 + v) * KS + s) * 4 + g] =
-                  lds_comp[(wslot * 16 + col) * (CES / 8) + (v * KS + s) * 4 + g];
+              qrec[(v * KS + s) * 4 + g] = lds_comp[(wslot * 16 + col) * (CES / 8) + (v * KS + s) * 4 + g];
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -750,7 +827,10 @@ static hipError_t launch_stage_impl(const StageArgs& a, hipStream_t stream) {
   constexpr size_t comp_bytes =
       Pr::mixed ? sizeof(typename Pr::Op) / 8 * 4 * 16 * (5 * 32 * L::KS + 8) + 2 * sizeof(float) * 7 * 4 * 64 : 0;
   constexpr bool lds = tab_bytes + comp_bytes <= 160 * 1024 / stage_min_blocks<P, Pr>();
-  auto kern = a.flux == 1 ? stage_kernel<P, Pr, lds, true> : stage_kernel<P, Pr, lds, false>;
+  auto kern = a.flux == 1 ? stage_kernel<P, Pr, lds, true, false> : stage_kernel<P, Pr, lds, false, false>;
+  if constexpr (Pr::mixed) {
+    if (!a.rk) kern = a.flux == 1 ? stage_kernel<P, Pr, lds, true, true> : stage_kernel<P, Pr, lds, false, true>;
+  }
   int per_cu = 0;
   hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0);
   if (err != hipSuccess) return err;
