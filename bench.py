@@ -483,10 +483,18 @@ def cpu_model() -> str:
 
     try:
         txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
-        names = [ln.split(":", 1)[1].strip() for ln in txt.splitlines()
-                 if ln.strip().startswith(("Model name", "BIOS Model name"))]
+        fields = {}
+        for ln in txt.splitlines():
+            if ":" in ln:
+                k, v = ln.split(":", 1)
+                fields.setdefault(k.strip(), v.strip())
+        names = [fields[k] for k in ("Model name", "BIOS Model name") if fields.get(k)]
         if names:
-            return " / ".join(dict.fromkeys(names))
+            # the family / model / stepping numbers identify the part where a virtualised
+            # host reports only a generic model name
+            ids = ", ".join(f"{k.lower()} {fields[k]}" for k in ("CPU family", "Model", "Stepping") if fields.get(k))
+            extra = [fields[k] + " " + k.lower() for k in ("Socket(s)",) if fields.get(k)]
+            return " / ".join(dict.fromkeys(names)) + (f" ({ids})" if ids else "") + (f", {extra[0]}" if extra else "")
     except (OSError, subprocess.SubprocessError):
         pass
     try:
