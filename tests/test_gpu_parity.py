@@ -340,8 +340,8 @@ def test_rk_step_mixed_multistep(p, prec):
         s.rk_stage(U2, Ub, U1, 1.0 / 3.0, dt)
         Ub.copy_(U1)
     s.sync()
-    # the mesh's elements (the padding columns of the tile are never stored by a stage, so
-    # they keep set_state's copy of element 0 in Ua and U1's zeros in Ub)
+    # compared on the mesh's elements (elements past the mesh, which pad the arrays to a
+    # multiple of the tile width, are not part of the result)
     assert torch.equal(s.get_state(Ua), s.get_state(Ub))
     got = s.get_state(Ua).cpu()
     ref = U
