@@ -162,7 +162,7 @@ int tdg_mesh_stats(const tdg_ctx* ctx, int64_t out[7]);
  * innermost (modes past N_p are padding, written as zero by set_state/project).  double for
  * TDG_FP64 and the mixed modes, float for TDG_FP32.  Elements n_elem .. n_elem_pad - 1 pad
  * the arrays to the kernels' tile width and carry no result: the compute calls leave them
- * unchanged in their outputs (FP64, FP32) or write zeros there (mixed modes).
+ * unchanged in their outputs or write zeros there.
  * User state:     [n_elem][5][N_p] double, caller's element order. */
 int tdg_state_elems(const tdg_ctx* ctx, int64_t* n_elem_pad);
 int tdg_state_bytes(const tdg_ctx* ctx, size_t* bytes);

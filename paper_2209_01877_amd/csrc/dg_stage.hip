@@ -59,8 +59,8 @@ constexpr int stage_min_blocks() {
 
 // kLds: reference tables staged in LDS; kRoe: Roe's interface flux instead of Rusanov's
 // (a compile-time choice keeps the other flux's code and registers out of the kernel).
-// kResid (mixed modes only): the residual without the RK update, a compile-time choice so
-// that the epilogue's state reads sit in no branch.
+// kResid (mixed modes; FP32 / FP64 up to P3): the residual without the RK update, a
+// compile-time choice so that the epilogue's state reads sit in no branch.
 template <int P, class Pr, bool kLds, bool kRoe, bool kResid>
 __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel(StageArgs a) {
   using O = Ord<P>;
@@ -534,13 +534,15 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
       asm("" : "+v"(x));
       return x;
     };
-    // Mixed modes (kFlat): the state reads and the stores of the result are unconditional.
+    // Mixed modes, and FP32 / FP64 up to P3 (kFlat): the state reads and the stores of the
+    // result are unconditional.  (At P4 the FP32 / FP64 kernels keep the branches: without
+    // them they spill more.)
     // Loads inside lane-dependent or uniform branches keep the compiler from counting the
     // outstanding loads across the branch, so that every later wait also waits for them.
     // Padding elements (e >= n_elem, inside the padded arrays) read valid memory and store
     // zeros; stage 1 (alpha = 0) reads U_in in place of U0 and multiplies it by zero.
-    constexpr bool kFlat = Pr::mixed;
-    const bool rk = Pr::mixed ? !kResid : a.rk != 0;
+    constexpr bool kFlat = Pr::mixed || P <= 3;
+    const bool rk = kFlat ? !kResid : a.rk != 0;
     const char* const u0src = a.alpha != 0.0 ? u0base : ubase;
     auto load_tail = [&]() {
 #pragma unroll
@@ -580,7 +582,17 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
         // uniform base of the variable + a 32-bit per-lane offset (one register, and the
         // loads' scalar-base addressing form)
         const size_t vb = (size_t)v * var_bytes;
-        if constexpr (kFlat) {
+        if constexpr (kFlat && Pr::f64) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int qd = 4 * mt + j;
+            if (qd < NPQ) {
+              const uint32_t o = lane_off(eoff + (uint32_t)qd * quad_bytes + (uint32_t)g * sizeof(S));
+              uin[v][j] = double(*reinterpret_cast<const S*>(ubase + vb + o));
+              u0v[v][j] = double(*reinterpret_cast<const S*>(u0src + vb + o));
+            }
+          }
+        } else if constexpr (kFlat) {
           // quads past the last read the last one and count as zero
           const int qd = 4 * mt + g;
           const uint32_t o = lane_off(eoff + (uint32_t)(qd < NPQ ? qd : NPQ - 1) * quad_bytes);
@@ -828,7 +840,7 @@ static hipError_t launch_stage_impl(const StageArgs& a, hipStream_t stream) {
       Pr::mixed ? sizeof(typename Pr::Op) / 8 * 4 * 16 * (5 * 32 * L::KS + 8) + 2 * sizeof(float) * 7 * 4 * 64 : 0;
   constexpr bool lds = tab_bytes + comp_bytes <= 160 * 1024 / stage_min_blocks<P, Pr>();
   auto kern = a.flux == 1 ? stage_kernel<P, Pr, lds, true, false> : stage_kernel<P, Pr, lds, false, false>;
-  if constexpr (Pr::mixed) {
+  if constexpr (Pr::mixed || P <= 3) {  // the kernel's kFlat
     if (!a.rk) kern = a.flux == 1 ? stage_kernel<P, Pr, lds, true, true> : stage_kernel<P, Pr, lds, false, true>;
   }
   int per_cu = 0;
