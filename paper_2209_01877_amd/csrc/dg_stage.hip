@@ -363,18 +363,12 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
         Acc dm[5], dp[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v) dm[v] = dp[v] = Acc{0, 0, 0, 0};
-        // own trace B_f c (the mixed modes re-read their operands, which are then
-        // consumed after the neighbour trace so that the read latency is covered)
+        // own trace B_f c, from the operands kept in registers since the group's start
         Op own[5][KS];
 #pragma unroll
         for (int v = 0; v < 5; ++v)
 #pragma unroll
-          for (int s = 0; s < KS; ++s) {
-            if constexpr (Pr::mixed)
-              own[v][s] = reinterpret_cast<const Op*>(a.q_in)[(((int64_t)e * 5 + v) * KS + s) * 4 + g];
-            else
-              own[v][s] = bc[v][s];
-          }
+          for (int s = 0; s < KS; ++s) own[v][s] = bc[v][s];
         // neighbour trace B_{f+} c+: the table depends on the neighbour's local face f+, which
         // varies by column; for every f+ present in the 16 columns the B operand is masked to
         // the columns having that f+, so all candidates accumulate into one result
