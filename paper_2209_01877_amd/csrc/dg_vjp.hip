@@ -354,6 +354,10 @@ __global__ __launch_bounds__(256, (vjp_min_blocks<P, Pr>())) void vjp_kernel(Vjp
     for (int i = 0; i < 9; ++i) Mt[i] = T(Md[i]);
     const T ivol = T(mv.inv_vol[e]);
     const int fcode = mv.fcode[e];
+    // the four neighbours, requested with the element's own data (not at each face)
+    int nbr[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) nbr[f] = mv.nbr[f * epad + e];
 
     Op bc[5][KS], bw[5][KS];
     load_ops<Pr, NP, KS>(ubase, var_bytes, eoff, off, keep, T(1), bc);
@@ -420,7 +424,7 @@ __global__ __launch_bounds__(256, (vjp_min_blocks<P, Pr>())) void vjp_kernel(Vjp
       T N[3];
       face_normal<T>(f, Md, N);
       const T nn = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
-      const int nbf = mv.nbr[f * epad + e];
+      const int nbf = f == 0 ? nbr[0] : f == 1 ? nbr[1] : f == 2 ? nbr[2] : nbr[3];
       const int fpl = (fcode >> (2 * f)) & 3;
       const int en = nbf >= 0 ? nbf : e;
       const uint32_t enoff = (uint32_t)en * 4 * sizeof(S);
