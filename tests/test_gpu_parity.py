@@ -132,6 +132,29 @@ def test_deterministic():
     assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("p", [2, 3, 4])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16"])
+def test_padding_elements_of_outputs(p, prec):
+    """Elements past the mesh (the arrays are padded to the tile width) carry no result: the
+    compute calls leave them unchanged or write zeros there, and never a non-finite value.
+    The ragged mesh (360 tets) pads 24 elements."""
+    mesh = make_mesh("ragged")
+    dg = oracle(p, mesh)
+    U = random_state(dg)
+    s = solver(p, prec, mesh)
+    assert s.n_elem_pad > s.n_elem
+    Ui = s.set_state(U.cuda())
+    before = Ui[:, :, s.n_elem:].clone()
+    R = s.residual(Ui)
+    s.rk_step(Ui, 0.5 * dg.stable_dt(U), 2)
+    s.sync()
+    # R starts as zeros (new_state), so either way its padding is zero
+    assert not R[:, :, s.n_elem:].any()
+    pad = Ui[:, :, s.n_elem:]
+    assert torch.isfinite(pad).all()
+    assert torch.equal(pad, before) or not pad.any(), "padding neither unchanged nor zero"
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
 def test_stable_dt(prec):
     """GPU minimum of the local time steps against the oracle's."""
