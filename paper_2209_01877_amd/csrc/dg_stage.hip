@@ -777,26 +777,43 @@ __global__ __launch_bounds__(256) void pack_kernel(MeshView m, const double* __r
   constexpr int NP = O::NP, REC = 32 * Layout<P, 8>::KS, NPQ = npq_of(NP), RQ = REC / 4;
   __shared__ E1 rec[64 * 5 * REC];
   const int64_t e0 = (int64_t)blockIdx.x * 64;
-  for (int i = threadIdx.x; i < 5 * RQ * 64; i += blockDim.x) {
-    const int el = i % 64, k = (i / 64) % RQ, v = i / (64 * RQ);
-    const int64_t e = e0 + el;
-    typedef double d4v_t __attribute__((ext_vector_type(4)));
-    d4v_t x = {0.0, 0.0, 0.0, 0.0};
-    if (k < NPQ) x = *reinterpret_cast<const d4v_t*>(u + ((int64_t)(v * NPQ + k) * m.epad + e) * 4);
-    typedef E1 e4v_t __attribute__((ext_vector_type(4)));
-    e4v_t h;
+  typedef double d4v_t __attribute__((ext_vector_type(4)));
+  typedef E1 e4v_t __attribute__((ext_vector_type(4)));
+  // all of a thread's state reads are issued before the first conversion
+  constexpr int NL = 5 * NPQ * 64, NIT = (NL + 255) / 256;
+  d4v_t x[NIT];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int mode = 4 * k + j;
-      h[j] = (mode > 0 && mode < NP) ? to_operand<E1>(x[j]) : (E1)0.0f;
+  for (int it = 0; it < NIT; ++it) {
+    const int i = (int)threadIdx.x + 256 * it;
+    if (i < NL) {
+      const int el = i % 64, vk = i / 64;  // vk = v * NPQ + k
+      x[it] = *reinterpret_cast<const d4v_t*>(u + ((int64_t)vk * m.epad + e0 + el) * 4);
     }
-    *reinterpret_cast<e4v_t*>(rec + (el * 5 + v) * REC + 4 * k) = h;
-    if (k == 0) c0[v * m.epad + e] = float(x[0]);
+  }
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int i = (int)threadIdx.x + 256 * it;
+    if (i < NL) {
+      const int el = i % 64, vk = i / 64, v = vk / NPQ, k = vk % NPQ;
+      e4v_t h;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int mode = 4 * k + j;
+        h[j] = (mode > 0 && mode < NP) ? to_operand<E1>(x[it][j]) : (E1)0.0f;
+      }
+      *reinterpret_cast<e4v_t*>(rec + (el * 5 + v) * REC + 4 * k) = h;
+      if (k == 0) c0[v * m.epad + e0 + el] = float(x[it][0]);
+    }
+  }
+  // the record slots past the last mode quad
+  for (int i = threadIdx.x; i < 5 * (RQ - NPQ) * 64; i += 256) {
+    const int el = i % 64, r = i / 64, v = r / (RQ - NPQ), k = NPQ + r % (RQ - NPQ);
+    *reinterpret_cast<e4v_t*>(rec + (el * 5 + v) * REC + 4 * k) = e4v_t{(E1)0.0f, (E1)0.0f, (E1)0.0f, (E1)0.0f};
   }
   __syncthreads();
   const uint4* src = reinterpret_cast<const uint4*>(rec);
   uint4* dst = reinterpret_cast<uint4*>(q + e0 * 5 * REC);
-  for (int i = threadIdx.x; i < 64 * 5 * REC * (int)sizeof(E1) / 16; i += blockDim.x) dst[i] = src[i];
+  for (int i = threadIdx.x; i < 64 * 5 * REC * (int)sizeof(E1) / 16; i += 256) dst[i] = src[i];
 }
 
 size_t companion_bytes(int p, int64_t epad) {
