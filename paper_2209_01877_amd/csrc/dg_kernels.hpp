@@ -148,6 +148,10 @@ __device__ __forceinline__ void rusanov_n(const T um[5], const T up[5], const T 
 // Roe flux through an area-weighted normal N (|N| = nn): central part minus
 // |N|/2 sum_k |lambda_k| alpha_k r_k with Roe averages (sqrt(rho) weights), acoustic
 // waves u.n -+ c (Harten entropy fix of width 0.1 c), entropy and shear waves at u.n.
+// The sum over the waves is regrouped with the acoustic pair's sum k1 + k4 and
+// difference k4 - k1 (r_{1,4} = r_2 -+ c (0, n, u.n)), and every sum of one-sided
+// terms is symmetric in the two states, so that, as for Rusanov's flux, exchanging the
+// states and negating the normal negates the flux exactly.
 template <class T>
 __device__ __forceinline__ void roe_n(const T um[5], const T up[5], const T N[3], T nn, T gamma, T out[5]) {
 #pragma clang fp contract(off)
@@ -157,51 +161,56 @@ __device__ __forceinline__ void roe_n(const T um[5], const T up[5], const T N[3]
   const T irl = prec_rcp(um[0]), irr = prec_rcp(up[0]);
   const T ul[3] = {um[1] * irl, um[2] * irl, um[3] * irl};
   const T ur[3] = {up[1] * irr, up[2] * irr, up[3] * irr};
-  const T pl = gm1 * (um[4] - T(0.5) * um[0] * (ul[0] * ul[0] + ul[1] * ul[1] + ul[2] * ul[2]));
-  const T pr = gm1 * (up[4] - T(0.5) * up[0] * (ur[0] * ur[0] + ur[1] * ur[1] + ur[2] * ur[2]));
-  const T hl = (um[4] + pl) * irl, hr = (up[4] + pr) * irr;
+  // p = (gamma - 1) (E - m.u / 2); el, er = E + p = rho H
+  const T pl = gm1 * fmaT(T(-0.5), fmaT(um[1], ul[0], fmaT(um[2], ul[1], um[3] * ul[2])), um[4]);
+  const T pr = gm1 * fmaT(T(-0.5), fmaT(up[1], ur[0], fmaT(up[2], ur[1], up[3] * ur[2])), up[4]);
+  const T el = um[4] + pl, er = up[4] + pr;
   const T sl = prec_sqrt(um[0]), sr = prec_sqrt(up[0]);
   const T iw = prec_rcp(sl + sr);
+  const T wl = sl * iw, wr = sr * iw;
   const T rho = sl * sr;
   T u[3], du[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    u[d] = (sl * ul[d] + sr * ur[d]) * iw;
+    u[d] = wl * ul[d] + wr * ur[d];
     du[d] = ur[d] - ul[d];
   }
-  const T h = (sl * hl + sr * hr) * iw;
-  const T q2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-  const T c = prec_sqrt(gm1 * (h - T(0.5) * q2));
-  const T ic2 = prec_rcp(c * c);
-  const T un = u[0] * n[0] + u[1] * n[1] + u[2] * n[2];
+  const T h = wl * (el * irl) + wr * (er * irr);
+  const T q2 = fmaT(u[0], u[0], fmaT(u[1], u[1], u[2] * u[2]));
+  const T c = prec_sqrt(gm1 * fmaT(T(-0.5), q2, h));
+  const T hic2 = T(0.5) * prec_rcp(c * c);
+  const T un = fmaT(u[0], n[0], fmaT(u[1], n[1], u[2] * n[2]));
   const T dr = up[0] - um[0], dp = pr - pl;
-  const T dun = du[0] * n[0] + du[1] * n[1] + du[2] * n[2];
+  const T dun = fmaT(du[0], n[0], fmaT(du[1], n[1], du[2] * n[2]));
+  // Harten: |lambda| -> (lambda^2 + del^2) / (2 del) inside |lambda| < del
   const T del = T(0.1) * c;
+  const T dd = del * del, hid = T(0.5) * prec_rcp(del);
   auto fix = [&](T lam) {
     const T a = fabs(lam);
-    return a < del ? (lam * lam + del * del) * T(0.5) * prec_rcp(del) : a;
+    return a < del ? fmaT(lam, lam, dd) * hid : a;
   };
   const T l1 = fix(un - c), l2 = fabs(un), l4 = fix(un + c);
-  const T a1 = (dp - rho * c * dun) * T(0.5) * ic2;
-  const T a2 = dr - dp * ic2;
-  const T a4 = (dp + rho * c * dun) * T(0.5) * ic2;
+  const T rc = rho * c;
+  const T a1 = fmaT(-rc, dun, dp) * hic2;
+  const T a2 = fmaT(-dp, T(2) * hic2, dr);
+  const T a4 = fmaT(rc, dun, dp) * hic2;
   const T k1 = l1 * a1, k2 = l2 * a2, k3 = l2 * rho, k4 = l4 * a4;
-  const T udu = u[0] * du[0] + u[1] * du[1] + u[2] * du[2];
+  const T ks = k1 + k4, kdc = (k4 - k1) * c;
+  const T udu = fmaT(u[0], du[0], fmaT(u[1], du[1], u[2] * du[2]));
   T diss[5];
-  diss[0] = k1 + k2 + k4;
+  diss[0] = ks + k2;
 #pragma unroll
-  for (int d = 0; d < 3; ++d)
-    diss[1 + d] = k1 * (u[d] - c * n[d]) + k2 * u[d] + k3 * (du[d] - dun * n[d]) + k4 * (u[d] + c * n[d]);
-  diss[4] = k1 * (h - un * c) + k2 * T(0.5) * q2 + k3 * (udu - un * dun) + k4 * (h + un * c);
+  for (int d = 0; d < 3; ++d) diss[1 + d] = fmaT(diss[0], u[d], fmaT(kdc, n[d], k3 * fmaT(-dun, n[d], du[d])));
+  diss[4] = fmaT(ks, h, fmaT(kdc, un, fmaT(k2, T(0.5) * q2, k3 * fmaT(-un, dun, udu))));
   // central part with the area-weighted normal
-  const T unl = ul[0] * N[0] + ul[1] * N[1] + ul[2] * N[2];
-  const T unr = ur[0] * N[0] + ur[1] * N[1] + ur[2] * N[2];
-  const T hh = T(0.5);
-  out[0] = hh * (um[0] * unl + up[0] * unr) - hh * nn * diss[0];
+  const T unl = fmaT(ul[0], N[0], fmaT(ul[1], N[1], ul[2] * N[2]));
+  const T unr = fmaT(ur[0], N[0], fmaT(ur[1], N[1], ur[2] * N[2]));
+  const T hn = T(0.5) * nn;
+  out[0] = fmaT(T(0.5), um[0] * unl + up[0] * unr, -(hn * diss[0]));
 #pragma unroll
   for (int d = 0; d < 3; ++d)
-    out[1 + d] = hh * (um[1 + d] * unl + pl * N[d] + up[1 + d] * unr + pr * N[d]) - hh * nn * diss[1 + d];
-  out[4] = hh * ((um[4] + pl) * unl + (up[4] + pr) * unr) - hh * nn * diss[4];
+    out[1 + d] = fmaT(T(0.5), fmaT(um[1 + d], unl, pl * N[d]) + fmaT(up[1 + d], unr, pr * N[d]), -(hn * diss[1 + d]));
+  out[4] = fmaT(T(0.5), el * unl + er * unr, -(hn * diss[4]));
 }
 
 // Numerical flux chosen at compile time (Roe when kRoe, else Rusanov).
