@@ -85,6 +85,11 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
   // wave access consecutive 8-byte words
   typedef float f2v_t __attribute__((ext_vector_type(2)));
   __shared__ f2v_t lds_face[Pr::mixed ? 7 * 4 * 64 : 1];
+  // FP64 at P4 (tables in global memory, LDS otherwise unused): the neighbour operands of
+  // the current face wait in LDS instead of registers, one slot per lane (each lane reads
+  // back only what it wrote), which keeps the kernel within its registers
+  constexpr bool kNbrLds = Pr::f64 && P == 4;
+  __shared__ Op lds_nbr[kNbrLds ? 4 * 5 * KS * 64 : 1];
   const Op* __restrict__ tab;
   if constexpr (kLds) {
     const Op* src = reinterpret_cast<const Op*>(a.tab);
@@ -215,7 +220,7 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
     };
     Op bn[5][KS];
     T c0n[5];
-    load_nbr(0, bn, c0n);
+    if constexpr (!kNbrLds) load_nbr(0, bn, c0n);
     // mixed: lane group g's face (face g): the neighbour's cell mean (its load is issued here
     // and consumed after the volume integral)
     const int nbg = g == 0 ? nbr[0] : g == 1 ? nbr[1] : g == 2 ? nbr[2] : nbr[3];
@@ -345,6 +350,16 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
       const int nbf = f == 0 ? nbr[0] : f == 1 ? nbr[1] : f == 2 ? nbr[2] : nbr[3];
       const int fpl = (fcode >> (2 * f)) & 3;
       T fhbar[5];
+      Op* const nslot = lds_nbr + wslot * (5 * KS * 64) + lane;
+      if constexpr (kNbrLds) {
+        load_nbr(f, bn, c0nn);
+#pragma unroll
+        for (int v = 0; v < 5; ++v)
+#pragma unroll
+          for (int s = 0; s < KS; ++s) nslot[(v * KS + s) * 64] = bn[v][s];
+        // the reads below must come from LDS (not be forwarded from the registers)
+        asm volatile("" ::: "memory");
+      }
       if constexpr (Pr::mixed) {
         // face f's record, written by lane group f of this column
         const f2v_t* slot = lds_face + wslot * 64 + 16 * f + col;
@@ -380,7 +395,10 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
             for (int s = 0; s < KS; ++s) {
               const Op av = tab[L::trace(c, ft, s) * 64 + lane];
 #pragma unroll
-              for (int v = 0; v < 5; ++v) dp[v] = Pr::mfma(av, mine ? bn[v][s] : Op{}, dp[v]);
+              for (int v = 0; v < 5; ++v) {
+                const Op bv = kNbrLds ? nslot[(v * KS + s) * 64] : bn[v][s];
+                dp[v] = Pr::mfma(av, mine ? bv : Op{}, dp[v]);
+              }
             }
           }
         }
@@ -392,7 +410,7 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
         }
         // the neighbour operands are consumed: request the next face's while this face's
         // own trace, fluxes and lifting are computed
-        if (f < 3 && ft == FT - 1) load_nbr(f + 1, bn, c0nn);
+        if (!kNbrLds && f < 3 && ft == FT - 1) load_nbr(f + 1, bn, c0nn);
         // face flux (deviation) at the tile's points: fp32 values for KW = 1, packed operand
         // pairs for KW = 8 (the lift's B operand holds the four points in k = 8 g + 0..3)
         T fh[5][Pr::KW == 1 ? 4 : 1];
