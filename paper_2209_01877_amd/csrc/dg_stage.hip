@@ -52,9 +52,19 @@ struct LiftPair<Pr, true> {
   typedef E1 type __attribute__((ext_vector_type(2)));
 };
 
+// Workgroups per CU the stage kernel is compiled for: two (two waves per SIMD, at most
+// 256 registers per lane) for FP32 and the mixed modes up to P3 and for FP64 up to P2;
+// FP64 at P3 (~400 registers) and every P4 kernel run one wave per SIMD.
 template <int P, class Pr>
 constexpr int stage_min_blocks() {
-  return (P <= 3 && !Pr::f64) ? 2 : 1;
+  return (P <= 3 && !Pr::f64) || (P <= 2 && Pr::f64) ? 2 : 1;
+}
+
+// FP64 at P1, P2 (two waves per SIMD) and P4 (tables in global memory): the current face's
+// neighbour operands wait in LDS instead of registers.
+template <int P, class Pr>
+constexpr bool stage_nbr_lds() {
+  return Pr::f64 && P != 3;
 }
 
 // kLds: reference tables staged in LDS; kRoe: Roe's interface flux instead of Rusanov's
@@ -85,10 +95,10 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
   // wave access consecutive 8-byte words
   typedef float f2v_t __attribute__((ext_vector_type(2)));
   __shared__ f2v_t lds_face[Pr::mixed ? 7 * 4 * 64 : 1];
-  // FP64 at P4 (tables in global memory, LDS otherwise unused): the neighbour operands of
-  // the current face wait in LDS instead of registers, one slot per lane (each lane reads
-  // back only what it wrote), which keeps the kernel within its registers
-  constexpr bool kNbrLds = Pr::f64 && P == 4;
+  // the current face's neighbour operands in LDS (FP64 at P1, P2 and P4), one slot per
+  // lane (each lane reads back only what it wrote): this keeps the kernel within its
+  // registers (two waves per SIMD at P1 and P2; fewer spills at P4)
+  constexpr bool kNbrLds = stage_nbr_lds<P, Pr>();
   __shared__ Op lds_nbr[kNbrLds ? 4 * 5 * KS * 64 : 1];
   const Op* __restrict__ tab;
   if constexpr (kLds) {
@@ -867,7 +877,8 @@ static hipError_t launch_stage_impl(const StageArgs& a, hipStream_t stream) {
   // areas in the LDS share of one workgroup (160 KB per CU over the workgroups resident per CU)
   constexpr size_t comp_bytes =
       Pr::mixed ? sizeof(typename Pr::Op) / 8 * 4 * 16 * (5 * 32 * L::KS + 8) + 2 * sizeof(float) * 7 * 4 * 64 : 0;
-  constexpr bool lds = tab_bytes + comp_bytes <= 160 * 1024 / stage_min_blocks<P, Pr>();
+  constexpr size_t nbr_bytes = stage_nbr_lds<P, Pr>() ? sizeof(typename Pr::Op) * 4 * 5 * L::KS * 64 : 0;
+  constexpr bool lds = tab_bytes + comp_bytes + nbr_bytes <= 160 * 1024 / stage_min_blocks<P, Pr>();
   auto kern = a.flux == 1 ? stage_kernel<P, Pr, lds, true, false> : stage_kernel<P, Pr, lds, false, false>;
   if constexpr (Pr::mixed || P <= 3) {  // the kernel's kFlat
     if (!a.rk) kern = a.flux == 1 ? stage_kernel<P, Pr, lds, true, true> : stage_kernel<P, Pr, lds, false, true>;

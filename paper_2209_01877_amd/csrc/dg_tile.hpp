@@ -55,8 +55,6 @@ __device__ __forceinline__ void load_operands(const char* __restrict__ base, uin
   }
 }
 
-// Two workgroups per CU (two waves per SIMD, at most 256 registers per lane) where the
-// live state fits; fp64 and P4 keep one (their tables and operands need the registers).
 // Projection / lift MFMA for one mode tile: the 4x4x1 block form for the short last
 // tile of the fp32 path (see kTail4; fp64 handles that tile with tail_fma), else the
 // precision's 16x16 instruction.
