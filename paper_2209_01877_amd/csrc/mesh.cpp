@@ -269,12 +269,14 @@ std::vector<int64_t> curve(const HostMesh& m, bool hilbert) {
 
 }  // namespace
 
-// Within consecutive windows of 256 elements of a locality-preserving order, stable-sort
+// Within consecutive windows of 4096 elements of a locality-preserving order, stable-sort
 // the elements by the 8-bit code of their neighbours' local faces.  The stage kernel runs
 // one MFMA chain per distinct neighbour face table present in a 16-element tile, so tiles
-// with uniform codes cost less; a 256-element window keeps the elements spatially close.
+// with uniform codes cost less.  A window of 4096 leaves about 16 elements per code, so
+// most tiles are uniform, and its elements still lie in a compact region (about the set
+// a device-wide sweep works on at once); much larger windows lose that locality.
 void group_by_face_code(const HostMesh& m, std::vector<int64_t>& order) {
-  const size_t W = 256;
+  const size_t W = 4096;
   std::vector<std::pair<int, int64_t>> key;
   for (size_t s = 0; s < order.size(); s += W) {
     const size_t t = std::min(order.size(), s + W);
