@@ -269,14 +269,14 @@ std::vector<int64_t> curve(const HostMesh& m, bool hilbert) {
 
 }  // namespace
 
-// Within consecutive windows of 4096 elements of a locality-preserving order, stable-sort
+// Within consecutive windows of W elements of a locality-preserving order, stable-sort
 // the elements by the 8-bit code of their neighbours' local faces.  The stage kernel runs
 // one MFMA chain per distinct neighbour face table present in a 16-element tile, so tiles
-// with uniform codes cost less.  A window of 4096 leaves about 16 elements per code, so
-// most tiles are uniform, and its elements still lie in a compact region (about the set
-// a device-wide sweep works on at once); much larger windows lose that locality.
-void group_by_face_code(const HostMesh& m, std::vector<int64_t>& order) {
-  const size_t W = 4096;
+// with uniform codes cost less.  After a space-filling curve, W = 4096 leaves about 16
+// elements per code, so most tiles are uniform, and its elements still lie in a compact
+// region (about the set a device-wide sweep works on at once; much larger windows lose
+// that locality).  After RCM, whose point is a small bandwidth, W = 256 keeps it small.
+void group_by_face_code(const HostMesh& m, std::vector<int64_t>& order, size_t W) {
   std::vector<std::pair<int, int64_t>> key;
   for (size_t s = 0; s < order.size(); s += W) {
     const size_t t = std::min(order.size(), s + W);
@@ -307,7 +307,7 @@ std::vector<int64_t> renumber(const HostMesh& m, int mode, bool group_codes) {
     std::iota(order.begin(), order.end(), 0);
     return order;
   }
-  if (group_codes) group_by_face_code(m, order);
+  if (group_codes) group_by_face_code(m, order, mode == 1 ? 256 : 4096);
   return order;
 }
 
