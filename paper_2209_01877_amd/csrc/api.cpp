@@ -392,9 +392,11 @@ int tdg_mesh_upload(tdg_ctx* c, int64_t n_elem, const int64_t* elem_vid, const d
     std::vector<double> M, iv, x0j;
     msg = build_geometry(hm, M, iv, x0j);
     if (!msg.empty()) return fail(c, TDG_ERR_MESH, msg);
-    // the compute-bound fp64/fp32 kernels gain from fewer neighbour face tables per tile; the
-    // memory-bound mixed kernels keep the tighter spatial order
-    const std::vector<int64_t> order = renumber(hm, renumber_mode, !is_mixed(c));  // new -> old
+    // the compute-bound fp64/fp32 kernels gain from fewer neighbour face tables per tile, and
+    // so do the mixed kernels at P4 (two operand slots per table); the memory-bound mixed
+    // kernels up to P3 keep the tighter spatial order
+    const bool group_codes = !is_mixed(c) || c->p >= 4;
+    const std::vector<int64_t> order = renumber(hm, renumber_mode, group_codes);  // new -> old
     std::vector<int64_t> inv(n_elem);
     for (int64_t i = 0; i < n_elem; ++i) inv[order[i]] = i;
     const int64_t epad = (n_elem + 63) / 64 * 64;
