@@ -69,9 +69,12 @@ constexpr bool stage_nbr_lds() {
 
 // kLds: reference tables staged in LDS; kRoe: Roe's interface flux instead of Rusanov's
 // (a compile-time choice keeps the other flux's code and registers out of the kernel).
-// kResid (mixed modes; FP32 / FP64 up to P3): the residual without the RK update, a
-// compile-time choice so that the epilogue's state reads sit in no branch.
-template <int P, class Pr, bool kLds, bool kRoe, bool kResid>
+// kEpi, the epilogue's form (a compile-time choice, so that the epilogue's state reads sit
+// in no branch; mixed modes and FP32 / FP64 up to P3, the other kernels take kEpiRK and
+// branch): the RK stage update, the residual without it, or the update of a stage with
+// alpha = 0 (SSP-RK3's first), which does not read U0.
+enum : int { kEpiRK = 0, kEpiResid = 1, kEpiRK0 = 2 };
+template <int P, class Pr, bool kLds, bool kRoe, int kEpi>
 __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel(StageArgs a) {
   using O = Ord<P>;
   using L = Layout<P, Pr::KW>;
@@ -562,10 +565,10 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
     // Loads inside lane-dependent or uniform branches keep the compiler from counting the
     // outstanding loads across the branch, so that every later wait also waits for them.
     // Padding elements (e >= n_elem, inside the padded arrays) read valid memory and store
-    // zeros; stage 1 (alpha = 0) reads U_in in place of U0 and multiplies it by zero.
+    // zeros; a stage with alpha = 0 leaves U0 unread (kEpiRK0).
     constexpr bool kFlat = Pr::mixed || P <= 3;
-    const bool rk = kFlat ? !kResid : a.rk != 0;
-    const char* const u0src = a.alpha != 0.0 ? u0base : ubase;
+    constexpr bool kU0 = kEpi == kEpiRK;
+    const bool rk = kFlat ? kEpi != kEpiResid : a.rk != 0;
     auto load_tail = [&]() {
 #pragma unroll
       for (int v = 0; v < (kSpread ? 5 : 1); ++v) tin[v] = t0v[v] = 0.0;
@@ -574,7 +577,7 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
       for (int v = 0; v < (kSpread ? 5 : 1); ++v) {
         const uint32_t o = lane_off(eoff + (uint32_t)(4 * (MT - 1)) * quad_bytes + (uint32_t)g * sizeof(S));
         tin[v] = double(*reinterpret_cast<const S*>(ubase + (size_t)v * var_bytes + o));
-        t0v[v] = double(*reinterpret_cast<const S*>(u0src + (size_t)v * var_bytes + o));
+        if constexpr (kU0) t0v[v] = double(*reinterpret_cast<const S*>(u0base + (size_t)v * var_bytes + o));
       }
     };
     auto load_tile = [&](int mt) {
@@ -611,7 +614,7 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
             if (qd < NPQ) {
               const uint32_t o = lane_off(eoff + (uint32_t)qd * quad_bytes + (uint32_t)g * sizeof(S));
               uin[v][j] = double(*reinterpret_cast<const S*>(ubase + vb + o));
-              u0v[v][j] = double(*reinterpret_cast<const S*>(u0src + vb + o));
+              if constexpr (kU0) u0v[v][j] = double(*reinterpret_cast<const S*>(u0base + vb + o));
             }
           }
         } else if constexpr (kFlat) {
@@ -619,11 +622,12 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
           const int qd = 4 * mt + g;
           const uint32_t o = lane_off(eoff + (uint32_t)(qd < NPQ ? qd : NPQ - 1) * quad_bytes);
           const s4_t x = *reinterpret_cast<const s4_t*>(ubase + vb + o);
-          const s4_t y = *reinterpret_cast<const s4_t*>(u0src + vb + o);
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            uin[v][j] = qd < NPQ ? double(x[j]) : 0.0;
-            u0v[v][j] = qd < NPQ ? double(y[j]) : 0.0;
+          for (int j = 0; j < 4; ++j) uin[v][j] = qd < NPQ ? double(x[j]) : 0.0;
+          if constexpr (kU0) {
+            const s4_t y = *reinterpret_cast<const s4_t*>(u0base + vb + o);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) u0v[v][j] = qd < NPQ ? double(y[j]) : 0.0;
           }
         } else if constexpr (!Pr::f64) {
           const int qd = 4 * mt + g;
@@ -879,9 +883,12 @@ static hipError_t launch_stage_impl(const StageArgs& a, hipStream_t stream) {
       Pr::mixed ? sizeof(typename Pr::Op) / 8 * 4 * 16 * (5 * 32 * L::KS + 8) + 2 * sizeof(float) * 7 * 4 * 64 : 0;
   constexpr size_t nbr_bytes = stage_nbr_lds<P, Pr>() ? sizeof(typename Pr::Op) * 4 * 5 * L::KS * 64 : 0;
   constexpr bool lds = tab_bytes + comp_bytes + nbr_bytes <= 160 * 1024 / stage_min_blocks<P, Pr>();
-  auto kern = a.flux == 1 ? stage_kernel<P, Pr, lds, true, false> : stage_kernel<P, Pr, lds, false, false>;
+  auto kern = a.flux == 1 ? stage_kernel<P, Pr, lds, true, kEpiRK> : stage_kernel<P, Pr, lds, false, kEpiRK>;
   if constexpr (Pr::mixed || P <= 3) {  // the kernel's kFlat
-    if (!a.rk) kern = a.flux == 1 ? stage_kernel<P, Pr, lds, true, true> : stage_kernel<P, Pr, lds, false, true>;
+    if (!a.rk)
+      kern = a.flux == 1 ? stage_kernel<P, Pr, lds, true, kEpiResid> : stage_kernel<P, Pr, lds, false, kEpiResid>;
+    else if (a.alpha == 0.0)
+      kern = a.flux == 1 ? stage_kernel<P, Pr, lds, true, kEpiRK0> : stage_kernel<P, Pr, lds, false, kEpiRK0>;
   }
   int per_cu = 0;
   hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0);
