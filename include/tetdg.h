@@ -202,8 +202,12 @@ int tdg_residual(tdg_ctx* ctx, const void* U, void* R, void* hip_stream);
  * n_steps SSP-RK3 steps of size dt on U (internal, in place):
  *   U1 = U + dt R(U);  U2 = 3/4 U + 1/4 (U1 + dt R(U1));  U <- 1/3 U + 2/3 (U2 + dt R(U2)).
  * work: device buffer of tdg_work_bytes() bytes (two internal states, plus in the mixed
- * modes three low-precision operand companions).  One fused residual+update launch per
- * stage (mixed modes: plus one companion pass over U per call).
+ * modes three low-precision operand companions, and up to P3 one array of fp64 cell
+ * means).  One fused residual+update launch per stage (mixed modes: plus one companion
+ * pass over U per call).  In the mixed modes up to P3 the second stage stores
+ * W2 = 1/3 U + 2/3 U2 instead of U2 and the third computes U <- W2 + 2/3 dt R(U2) (the same
+ * update, rounded differently), so that it reads no U; U2 itself enters only through its
+ * companion and its cell means.
  * Errors: TDG_ERR_INVALID_ARG (NULL U or work, n_steps < 0), TDG_ERR_STATE, TDG_ERR_HIP. */
 int tdg_rk_step(tdg_ctx* ctx, void* U, void* work, double dt, int n_steps, void* hip_stream);
 

@@ -323,7 +323,16 @@ void comp_ptrs(const tdg_ctx* c, char* base, void** q, float** c0) {
   *c0 = (float*)(base + qb);
 }
 
-size_t work_bytes(const tdg_ctx* c) { return 2 * state_bytes(c) + 3 * comp_bytes(c); }
+// Mixed modes up to P3: rk_step's second stage stores W2 = U0/3 + 2 U2/3 instead of U2, so
+// that the third stage reads no U0 (at P4, whose stage kernel runs one wave per SIMD, that
+// measured no faster).
+bool split_rk3(const tdg_ctx* c) { return is_mixed(c) && c->p <= 3; }
+
+// rk_step's work buffer: the states U1 and U2, then (mixed modes) the companions of U, U1,
+// U2, then (split_rk3) the fp64 cell means of U2 ([5][E_pad]).
+size_t work_bytes(const tdg_ctx* c) {
+  return 2 * state_bytes(c) + 3 * comp_bytes(c) + (split_rk3(c) ? 5 * (size_t)c->epad * sizeof(double) : 0);
+}
 
 }  // namespace
 
@@ -646,6 +655,7 @@ static StageArgs stage_args(const tdg_ctx* c) {
   a.gamma = c->gamma;
   for (int v = 0; v < 5; ++v) a.far[v] = c->far[v];
   a.flux = c->flux;
+  a.dt_scale = 1.0;
   return a;
 }
 
@@ -723,6 +733,8 @@ int tdg_rk_step(tdg_ctx* c, void* U, void* work, double dt, int n_steps, void* s
   // mixed: operand companions of U, U1, U2 follow the two states
   void* q[3] = {nullptr, nullptr, nullptr};
   float* c0[3] = {nullptr, nullptr, nullptr};
+  // split_rk3: the fp64 cell means of U2 (the third stage's u_in holds W2, see below)
+  double* const means = split_rk3(c) ? (double*)(w + 2 * state_bytes(c) + 3 * comp_bytes(c)) : nullptr;
   if (is_mixed(c)) {
     for (int k = 0; k < 3; ++k) comp_ptrs(c, w + 2 * state_bytes(c) + k * comp_bytes(c), &q[k], &c0[k]);
     if (n_steps > 0) {
@@ -748,6 +760,17 @@ int tdg_rk_step(tdg_ctx* c, void* U, void* work, double dt, int n_steps, void* s
       a.c0_in = c0[qin[stg]];
       a.q_out = q[qout[stg]];
       a.c0_out = c0[qout[stg]];
+      // split_rk3: the second stage stores W2 = U0/3 + 2 U2/3 in place of U2 (U2's
+      // companion and fp64 cell means beside it), so that the third stage, U3 = W2 +
+      // (2/3) dt R(U2), reads no U0 (the same update as U0/3 + 2/3 (U2 + dt R(U2)))
+      a.alpha_w = means && stg == 1 ? 1.0 / 3.0 : 0.0;
+      a.mean_out = means && stg == 1 ? means : nullptr;
+      a.mean_in = means && stg == 2 ? means : nullptr;
+      a.dt_scale = means && stg == 2 ? 2.0 / 3.0 : 1.0;
+      if (means && stg == 2) {
+        a.alpha = 0.0;
+        a.u0 = nullptr;
+      }
       hipError_t e = viscous_part(c, a.u_in, a, (hipStream_t)s);
       if (e != hipSuccess) return hip_fail(c, e, "viscous launch");
       e = launch_stage(c->p, c->prec, a, (hipStream_t)s);
@@ -767,6 +790,8 @@ int tdg_rk_step_adaptive(tdg_ctx* c, void* U, void* work, double cfl, int n_step
   void* U2 = w + state_bytes(c);
   void* q[3] = {nullptr, nullptr, nullptr};
   float* c0[3] = {nullptr, nullptr, nullptr};
+  // split_rk3: the fp64 cell means of U2 (the third stage's u_in holds W2, see below)
+  double* const means = split_rk3(c) ? (double*)(w + 2 * state_bytes(c) + 3 * comp_bytes(c)) : nullptr;
   if (is_mixed(c)) {
     for (int k = 0; k < 3; ++k) comp_ptrs(c, w + 2 * state_bytes(c) + k * comp_bytes(c), &q[k], &c0[k]);
     if (n_steps > 0) {
@@ -796,6 +821,17 @@ int tdg_rk_step_adaptive(tdg_ctx* c, void* U, void* work, double cfl, int n_step
       a.c0_in = c0[qin[stg]];
       a.q_out = q[qout[stg]];
       a.c0_out = c0[qout[stg]];
+      // split_rk3: the second stage stores W2 = U0/3 + 2 U2/3 in place of U2 (U2's
+      // companion and fp64 cell means beside it), so that the third stage, U3 = W2 +
+      // (2/3) dt R(U2), reads no U0 (the same update as U0/3 + 2/3 (U2 + dt R(U2)))
+      a.alpha_w = means && stg == 1 ? 1.0 / 3.0 : 0.0;
+      a.mean_out = means && stg == 1 ? means : nullptr;
+      a.mean_in = means && stg == 2 ? means : nullptr;
+      a.dt_scale = means && stg == 2 ? 2.0 / 3.0 : 1.0;
+      if (means && stg == 2) {
+        a.alpha = 0.0;
+        a.u0 = nullptr;
+      }
       e = viscous_part(c, a.u_in, a, (hipStream_t)s);
       if (e != hipSuccess) return hip_fail(c, e, "viscous launch");
       e = launch_stage(c->p, c->prec, a, (hipStream_t)s);

@@ -30,6 +30,16 @@ struct StageArgs {
   const float* c0_in;
   void* q_out;
   float* c0_out;
+  // mixed modes, SSP-RK3 through rk_step (the update's algebra regrouped so that the third
+  // stage does not read U0): dt is multiplied by dt_scale; when alpha_w != 0 the stored
+  // result is alpha_w U0 + (1 - alpha_w) times the stage result, while the companion and
+  // mean_out ([5][E_pad] fp64 cell means) are of the stage result itself; when mean_in is
+  // non-null it holds the fp64 cell means of the state whose companion is q_in (u_in then
+  // holds another combination)
+  double dt_scale;
+  double alpha_w;
+  const double* mean_in;
+  double* mean_out;
 };
 
 struct VjpArgs {

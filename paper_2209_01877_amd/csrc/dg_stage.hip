@@ -71,9 +71,11 @@ constexpr bool stage_nbr_lds() {
 // (a compile-time choice keeps the other flux's code and registers out of the kernel).
 // kEpi, the epilogue's form (a compile-time choice, so that the epilogue's state reads sit
 // in no branch; mixed modes and FP32 / FP64 up to P3, the other kernels take kEpiRK and
-// branch): the RK stage update, the residual without it, or the update of a stage with
-// alpha = 0 (SSP-RK3's first), which does not read U0.
-enum : int { kEpiRK = 0, kEpiResid = 1, kEpiRK0 = 2 };
+// branch): the RK stage update, the residual without it, the update of a stage with
+// alpha = 0 (SSP-RK3's first), which does not read U0, or (mixed modes) the update that
+// stores alpha_w U0 + (1 - alpha_w) times the stage result and writes the result's fp64
+// cell means beside its companion.
+enum : int { kEpiRK = 0, kEpiResid = 1, kEpiRK0 = 2, kEpiRKW = 3 };
 template <int P, class Pr, bool kLds, bool kRoe, int kEpi>
 __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel(StageArgs a) {
   using O = Ord<P>;
@@ -143,7 +145,8 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
   const uint32_t quad_bytes = (uint32_t)(epad * 4 * sizeof(S));  // one (variable, mode quad) plane
   const uint32_t var_bytes = quad_bytes * NPQ;
   const T gamma = T(a.gamma), gm1 = T(a.gamma - 1.0);
-  const double dt = a.dt_dev ? *a.dt_dev : a.dt;  // step size (device-computed when adaptive)
+  // step size (device-computed when adaptive), times the stage's factor
+  const double dt = (a.dt_dev ? *a.dt_dev : a.dt) * a.dt_scale;
   T far[5];
   double far64[5];
 #pragma unroll
@@ -530,6 +533,11 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
     // state values (loads complete in order, so waiting for them then leaves the state
     // reads in flight)
     double mtab[Pr::mixed ? MT : 1][2];
+    // fp64 cell means of the stage's state: mode 0 of u_in, or mean_in when u_in holds
+    // another combination (a uniform choice of base and strides)
+    const char* const mbase = a.mean_in ? reinterpret_cast<const char*>(a.mean_in) : ubase;
+    const uint32_t mvs = a.mean_in ? (uint32_t)(epad * sizeof(double)) : var_bytes;
+    const uint32_t mes = a.mean_in ? (uint32_t)sizeof(double) : (uint32_t)(4 * sizeof(S));
     if constexpr (Pr::mixed) {
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
@@ -538,11 +546,10 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
       }
 #pragma unroll
       for (int i = 0; i < 9; ++i) Me[i] = mv.M[i * epad + e];
-      const uint32_t goff = (uint32_t)(ng >= 0 ? ng : e) * 4 * sizeof(S);
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
-        c0e[v] = double(*reinterpret_cast<const S*>(ubase + (size_t)v * var_bytes + eoff));
-        c0g[v] = double(*reinterpret_cast<const S*>(ubase + (size_t)v * var_bytes + goff));
+        c0e[v] = *reinterpret_cast<const double*>(mbase + (size_t)v * mvs + (uint32_t)e * mes);
+        c0g[v] = *reinterpret_cast<const double*>(mbase + (size_t)v * mvs + (uint32_t)(ng >= 0 ? ng : e) * mes);
       }
     }
     // State values of mode tile mt (mode = 16 mt + drow(g, j)): with the fp32 accumulator
@@ -567,7 +574,7 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
     // Padding elements (e >= n_elem, inside the padded arrays) read valid memory and store
     // zeros; a stage with alpha = 0 leaves U0 unread (kEpiRK0).
     constexpr bool kFlat = Pr::mixed || P <= 3;
-    constexpr bool kU0 = kEpi == kEpiRK;
+    constexpr bool kU0 = kEpi == kEpiRK || kEpi == kEpiRKW;
     const bool rk = kFlat ? kEpi != kEpiResid : a.rk != 0;
     auto load_tail = [&]() {
 #pragma unroll
@@ -709,7 +716,7 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
           mean = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, x1[v], mean, 0, 0, 0);
         }
         const bool spread = kSpread && mt == MT - 1;
-        double o[4];
+        double o[4], oc[4];  // stored values; values of the companion (the stage result)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int mode = spread ? (j == 0 ? 16 * mt + g : NP) : 16 * mt + drow_of<Pr>(g, j);
@@ -720,7 +727,10 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
           const double ui = spread ? tin[kSpread ? v : 0] : uin[v][j];
           const double u0 = spread ? t0v[kSpread ? v : 0] : u0v[v][j];
           const double out = rk ? a.alpha * u0 + (1.0 - a.alpha) * (ui + dt * r) : r;
-          o[j] = mode < NP && (!kFlat || live) ? out : 0.0;
+          double st = out;
+          if constexpr (kEpi == kEpiRKW) st = a.alpha_w * u0 + (1.0 - a.alpha_w) * out;
+          o[j] = mode < NP && (!kFlat || live) ? st : 0.0;
+          oc[j] = mode < NP && (!kFlat || live) ? out : 0.0;
         }
         if (!kFlat && !live) continue;
         char* const ob = obase + (size_t)v * var_bytes;
@@ -753,18 +763,21 @@ __global__ __launch_bounds__(256, (stage_min_blocks<P, Pr>())) void stage_kernel
             if (spread) {
               // mode 16 mt + g from every lane group (modes 16 mt + 4 .. 15 are padding, zero
               // since the kernel's start)
-              rec[g] = to_operand<E1>(o[0]);
+              rec[g] = to_operand<E1>(oc[0]);
             } else {
               e4_t h;
 #pragma unroll
               for (int j = 0; j < 4; ++j) {
                 const int mode = 16 * mt + 4 * g + j;
-                h[j] = mode > 0 ? to_operand<E1>(o[j]) : (E1)0.0f;
+                h[j] = mode > 0 ? to_operand<E1>(oc[j]) : (E1)0.0f;
               }
               // modes 16 mt + 4 g .. + 3 of (col, v) into this wave's staging record
               *reinterpret_cast<e4_t*>(rec + 4 * g) = h;
             }
-            if (mt == 0 && g == 0) a.c0_out[v * epad + e] = float(o[0]);
+            if (mt == 0 && g == 0) {
+              a.c0_out[v * epad + e] = float(oc[0]);
+              if constexpr (kEpi == kEpiRKW) a.mean_out[v * epad + e] = oc[0];
+            }
           }
         }
       }
@@ -889,6 +902,10 @@ static hipError_t launch_stage_impl(const StageArgs& a, hipStream_t stream) {
       kern = a.flux == 1 ? stage_kernel<P, Pr, lds, true, kEpiResid> : stage_kernel<P, Pr, lds, false, kEpiResid>;
     else if (a.alpha == 0.0)
       kern = a.flux == 1 ? stage_kernel<P, Pr, lds, true, kEpiRK0> : stage_kernel<P, Pr, lds, false, kEpiRK0>;
+  }
+  if constexpr (Pr::mixed) {
+    if (a.rk && a.alpha != 0.0 && a.alpha_w != 0.0)
+      kern = a.flux == 1 ? stage_kernel<P, Pr, lds, true, kEpiRKW> : stage_kernel<P, Pr, lds, false, kEpiRKW>;
   }
   int per_cu = 0;
   hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0);
