@@ -72,7 +72,8 @@ constexpr bool stage_nbr_lds() {
 // kEpi, the epilogue's form (a compile-time choice, so that the epilogue's state reads sit
 // in no branch; mixed modes and FP32 / FP64 up to P3, the other kernels take kEpiRK and
 // branch): the RK stage update, the residual without it, the update of a stage with
-// alpha = 0 (SSP-RK3's first), which does not read U0, or (mixed modes) the update that
+// alpha = 0 (SSP-RK3's first, and the mixed modes' regrouped third), which does not read
+// U0, or (mixed modes) the update that
 // stores alpha_w U0 + (1 - alpha_w) times the stage result and writes the result's fp64
 // cell means beside its companion.
 enum : int { kEpiRK = 0, kEpiResid = 1, kEpiRK0 = 2, kEpiRKW = 3 };
