@@ -340,7 +340,7 @@ def test_temporal_mixed_precision():
     print("MP-N increment errors vs the FP64 oracle:", errs)
 
 
-@pytest.mark.parametrize("p", [2, 4])
+@pytest.mark.parametrize("p", [2, 3, 4])
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
 def test_rk_step_mixed_multistep(p, prec):
     """Three SSP-RK3 steps in a mixed mode through tdg_rk_step, where each stage kernel writes
